@@ -1,0 +1,122 @@
+"""The workload shapes the library is exercised and measured on.
+
+Each builder returns a Workload with every input of one XC integration:
+atoms (coordinates and Mura-Knowles radial scale), basis, density matrix and
+grid parameters. Grid sizes follow the paper's Table 2 shapes (75 x 302,
+99 x 590) plus 100 x 590 for the water cluster; screening tolerance 1e-10 and
+batches of at most 512 points follow Sec. 2.2.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .angular import lebedev_table
+from .basis import BasisSet, make_basis, overlap_matrix
+from .density import random_density, perturbed_density
+from .molecules import Molecule, water, water_cluster, peptide_chain
+
+# Mura-Knowles radial scale per element (5.0 for H, C, N, O).
+MK_ALPHA = {1: 5.0, 6: 5.0, 7: 5.0, 8: 5.0}
+
+
+@dataclass
+class Workload:
+    name: str
+    mol: Molecule
+    basis: BasisSet
+    P: np.ndarray
+    n_occ: int
+    n_rad: int
+    n_ang: int
+    functional: str                 # "lda" (Slater + VWN5) or "pbe"
+    S: np.ndarray = None
+    ssf_a: float = 0.64
+    screen_eta: float = 1e-10
+    batch_max: int = 512
+    rho_thresh: float = 1e-15
+    ang: np.ndarray = field(default=None, repr=False)
+
+    def __post_init__(self):
+        if self.ang is None:
+            self.ang = lebedev_table(self.n_ang)
+
+    @property
+    def coords(self):
+        return self.mol.coords
+
+    @property
+    def mk_alpha(self):
+        return np.array([MK_ALPHA[int(z)] for z in self.mol.Z])
+
+    @property
+    def natoms(self):
+        return self.mol.natoms
+
+    @property
+    def nbf(self):
+        return self.basis.nbf
+
+    @property
+    def n_points_nominal(self):
+        return self.natoms * self.n_rad * self.n_ang
+
+
+def grid_spec_dict(w, atom_mask=None, **over):
+    d = dict(n_rad=w.n_rad, n_ang=w.n_ang, ang=w.ang, ssf_a=w.ssf_a,
+             screen_eta=w.screen_eta, batch_max=w.batch_max,
+             rho_thresh=w.rho_thresh, atom_mask=atom_mask)
+    d.update(over)
+    return d
+
+
+def _finish(name, mol, n_occ, n_rad, n_ang, functional, seed, diffuse=None,
+            with_S=True):
+    basis = make_basis(mol.Z, seed=2007, diffuse=diffuse)
+    S = overlap_matrix(basis, mol.coords)
+    P = random_density(S, n_occ, seed=seed)
+    return Workload(name, mol, basis, P, n_occ, n_rad, n_ang, functional,
+                    S=S if with_S else None)
+
+
+def cfg_water(functional="lda", n_rad=75, n_ang=302, seed=1):
+    """One water, ~25 functions, 5 occupied orbitals (tr PS = 10),
+    75 x 302 grid per atom (67,950 points)."""
+    return _finish("water", water(), 5, n_rad, n_ang, functional, seed)
+
+
+def cfg_water_cluster(n_waters=64, functional="pbe", n_rad=100, n_ang=590,
+                      seed=2, n_occ=None, box=None):
+    """n_waters rigid waters in a box (25 bohr for 64, scaled with the cube
+    root of the count otherwise), minimum O-O distance 5 bohr."""
+    if box is None:
+        box = 25.0 * (n_waters / 64.0) ** (1.0 / 3.0)
+    if n_occ is None:
+        n_occ = 4 * n_waters
+    mol = water_cluster(n_waters, box=box, seed=seed)
+    return _finish(f"water{n_waters}", mol, n_occ, n_rad, n_ang, functional,
+                   seed)
+
+
+def cfg_chain(n_atoms=600, functional="pbe", n_rad=99, n_ang=590, seed=4):
+    """Polypeptide-like chain with one extra diffuse s shell (exponent 0.04)
+    per atom."""
+    mol = peptide_chain(n_atoms, seed=seed)
+    n_occ = mol.n_electrons // 2
+    return _finish(f"chain{n_atoms}", mol, n_occ, n_rad, n_ang, functional,
+                   seed, diffuse=0.04)
+
+
+def cfg_serving_request(index, seed=5, n_rad=75, n_ang=302):
+    """One request of the serving stream: a water cluster of 1-100 waters
+    (log-uniform), LDA or PBE (50/50), and 6-12 SCF densities
+    P_k = P_0 + delta_k with |delta_k|_F = 1e-3."""
+    rng = np.random.default_rng([seed, index])
+    n_w = int(np.clip(np.round(np.exp(rng.uniform(0.0, np.log(100.0)))), 1, 100))
+    func = "lda" if rng.uniform() < 0.5 else "pbe"
+    n_iter = int(rng.integers(6, 13))
+    w = cfg_water_cluster(n_w, functional=func, n_rad=n_rad, n_ang=n_ang,
+                          seed=seed * 100003 + index, n_occ=5 * n_w)
+    w.name = f"req{index}_water{n_w}"
+    dens = [perturbed_density(w.P, 1e-3, seed=seed * 7919 + index * 31 + k)
+            for k in range(n_iter)]
+    return w, dens

@@ -1,0 +1,182 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the XC integration on one MI355X.
+
+Workload (default): the 64-water cluster, 192 atoms, 1600 Cartesian basis
+functions, 100 x 590 Mura-Knowles x Lebedev grid per atom (11,328,000
+nominal points), PBE, FP64, seeded synthetic inputs.
+
+One step is the whole path on device-resident inputs: grid points, SSF
+weights, removal of zero-weight points, batching, shell screening, wave
+plan, collocation, X = P Phi with rho/grad rho, functional, Z, and
+V = Z Phi^T + Phi Z^T with scatter-add, mirror and the E_xc/N_e sums.
+value = nominal grid points / step time. The same line reports the warm
+(grid reused, Sec. 2.3.1) rate, the roofline of the dominant kernel from
+HIP-event timing inside the timed region, and the CPU oracle timed on a
+bounded sample of the same workload.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = ("grid points/s for E_xc+V_xc (FP64 vs mixed at stated err); "
+          "p50/p99 req latency")
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from workloads import cfg_water_cluster, cfg_chain, cfg_water
+    if name == "water64":
+        return cfg_water_cluster(), "pbe"
+    if name == "chain600":
+        return cfg_chain(), "pbe"
+    if name == "water":
+        return cfg_water(functional="lda"), "lda"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, functional, stride):
+    """The oracle, as it is, on a strided sample of parent atom 0's grid."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    mask = np.zeros(w.natoms, bool)
+    mask[0] = True
+    sl = slice(0, None, stride)
+    n_atom = w.n_rad * w.n_ang
+    n_sample = len(range(*sl.indices(n_atom)))
+    t0 = time.perf_counter()
+    oracle.integrate(w.coords, w.mk_alpha, w.basis, w.P, functional, w.n_rad, w.ang,
+                     atom_mask=mask, point_slice=sl,
+                     progress=lambda s, d, t: log(f"  oracle {s} {d}/{t}"))
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "grid points/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{n_sample} points (every {stride}th point of parent atom 0's "
+                      f"{n_atom}-point grid) of the same workload, SSF over all "
+                      f"{w.natoms} atoms, {w.nbf} functions, {functional}; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="water64")
+    ap.add_argument("--wave-gb", type=float, default=0.0)
+    ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU's share only; runs on more than one GPU "
+              "are not part of this build (see the sharding design).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2007_03143_amd import XcContext
+    from workloads import grid_spec_dict
+
+    log(f"building workload {args.workload}")
+    w, functional = make_workload(args.workload)
+    ctx = XcContext(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w),
+                    wave_bytes=int(args.wave_gb * (1 << 30)))
+    P = torch.from_numpy(w.P).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        ctx.build_grid()
+        ctx.integrate(P, functional)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    st = ctx.stats()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = ctx.timing()
+    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    n_nom = w.n_points_nominal
+    value = n_nom / (ms_step * 1e-3)
+
+    # warm: grid, weights, batches and screening lists reused
+    ctx.set_timing(False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.integrate(P, functional)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ms_warm = (t3 - t2) * 1e3 / args.steps
+    EN = ctx.EN.cpu().numpy()
+    V = ctx.V.cpu().numpy()
+    log(f"warm {ms_warm:.1f} ms/step; E_xc {EN[0]!r} N_e {EN[1]!r}")
+
+    # roofline of the dominant kernel (HIP events inside the timed region)
+    flops = {"density": 2.0 * st["sum_nb2_ng"],
+             "potential": 2.0 * (st["sum_nb2_ng"] + st["sum_nb_ng"])}
+    phase_ms = {k: v["ms"] / args.steps for k, v in timing.items()}
+    dom = max(phase_ms, key=phase_ms.get)
+    if dom in flops:
+        achieved = flops[dom] / (phase_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": dom, "achieved": achieved,
+                "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
+                "flops_per_step": flops[dom],
+                "launches_per_step": timing[dom]["launches"] / args.steps}
+    else:
+        roof = {"bound": "alu", "kernel": dom, "achieved": None,
+                "peak": None, "unit": None, "frac": None, "traffic": None}
+    contract_ms = phase_ms["density"] + phase_ms["potential"]
+    both = (flops["density"] + flops["potential"]) / (contract_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name} {functional} {w.n_rad}x{w.n_ang}",
+                   "natoms": w.natoms, "nbf": w.nbf, "n_points_nominal": n_nom,
+                   "n_points_kept": st["n_points"], "n_batches": st["n_batches"],
+                   "mean_nb_point_weighted": st["sum_nb_ng"] / max(st["n_points"], 1),
+                   "max_nb": st["max_nb"], "n_waves": st["n_waves"],
+                   "precision": "fp64", "parallelism": "single GPU",
+                   "step": "grid build + weights + batching + screening + integration"},
+        "warm": {"value": n_nom / (ms_warm * 1e-3), "ms_per_step": ms_warm,
+                 "step": "integration with the grid reused"},
+        "phase_ms_per_step": phase_ms,
+        "contractions_tflops": both,
+        "roofline": roof,
+        "E_xc": float(EN[0]), "N_e": float(EN[1]),
+        "V_symmetric": bool(np.array_equal(V, V.T)),
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a sample)")
+        out["cpu_baseline"] = cpu_baseline(w, functional, args.cpu_stride)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

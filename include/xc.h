@@ -1,0 +1,256 @@
+/*
+ * xc.h - C ABI of the MI355X (gfx950) library for the numerical integration
+ * of the Kohn-Sham exchange-correlation energy E_xc and potential matrix V_xc
+ * over an atom-centred molecular grid in a Cartesian Gaussian basis
+ * (arXiv 2007.03143, Sec. 2.1-2.3).
+ *
+ * What one integration computes (Sec. 2.1 eq. vxc_exact, eq. zvec_r;
+ * Sec. 2.2 eq. exc_batch, eq. vxc_inc, eq. vxc_batch, eq. z_mat):
+ *
+ *   rho_i   = sum_{mu nu} P_{mu nu} phi~_mu(r_i) phi~_nu(r_i)
+ *   grad_i  = 2 sum_{mu nu} P_{mu nu} grad phi~_mu(r_i) phi~_nu(r_i)
+ *   sigma_i = |grad_i|^2
+ *   E_xc    = sum_i w_i e(rho_i, sigma_i)        (points with rho_i >= rho_thresh)
+ *   N_e     = sum_i w_i rho_i                     (all points)
+ *   V_{mu nu} = sum_i w_i [ v_rho phi~_mu phi~_nu
+ *                 + 2 v_sigma grad_i . (phi~_mu grad phi~_nu + grad phi~_mu phi~_nu) ]
+ *
+ * with e = rho * eps the energy per unit volume, v_rho = de/drho,
+ * v_sigma = de/dsigma, phi~ the basis function truncated at its shell's
+ * cutoff radius (Sec. 2.2 eq. rcut) and w_i the Stratmann-Scuseria-Frisch
+ * scaled weights of the Mura-Knowles x Lebedev product grid
+ * (Sec. 2.2 eq. atomic_partition, eq. num_int).
+ *
+ * Units: bohr and hartree. Matrices are row-major nbf x nbf FP64.
+ *
+ * Errors: every function returns XC_OK (0) or a negative code; on error no
+ * output is written and xc_last_error() returns a message for the calling
+ * thread. No C++ exception crosses this boundary.
+ *
+ * Threading: one context must not be used from two threads at once;
+ * distinct contexts are independent.
+ */
+#ifndef XC_MI355X_H
+#define XC_MI355X_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XC_ABI_VERSION 1
+
+/* return codes */
+#define XC_OK               0
+#define XC_ERR_INVALID_ARG (-1)  /* a pointer, size or value is out of range */
+#define XC_ERR_UNSUPPORTED (-2)  /* L > 3, nprim > 16, unknown functional or precision */
+#define XC_ERR_NOMEM       (-3)  /* device memory exhausted or budget too small */
+#define XC_ERR_DEVICE      (-4)  /* a HIP runtime call or kernel launch failed */
+#define XC_ERR_STATE       (-5)  /* call not valid in the context's current state */
+
+/* exchange-correlation functionals (spin-unpolarised) */
+#define XC_LDA_SVWN5 1   /* Slater exchange + VWN5 correlation */
+#define XC_GGA_PBE   2   /* PBE exchange + PBE correlation (PW92 base) */
+
+/* arithmetic of the collocation and the two batched contractions */
+#define XC_FP64          0   /* everything FP64 */
+#define XC_MIXED_FP32    1   /* reserved: FP32 contractions, FP64 functional and sums */
+#define XC_MIXED_BF16X3  2   /* reserved: split-BF16 contractions with FP32 accumulate */
+
+/*
+ * Atoms (Sec. 2.2, eq. atomic_partition): centres R_A in bohr (natoms x 3,
+ * row-major) and the Mura-Knowles radial scale alpha_A of each atom's grid.
+ * Borrowed for the duration of the call only.
+ */
+typedef struct xc_molecule {
+    int natoms;
+    const double* xyz;        /* natoms x 3 */
+    const double* mk_alpha;   /* natoms, > 0 */
+} xc_molecule;
+
+/*
+ * Contracted Cartesian Gaussian shells (Sec. 2.1, eq. gau_cart). Shell s sits
+ * on atom shell_atom[s], has angular momentum shell_L[s] (0..3) and
+ * shell_nprim[s] (1..16) primitives; exponents and coefficients are packed
+ * in shell order and the coefficients are used as given (no normalisation
+ * is applied). A shell holds (L+1)(L+2)/2 functions ordered xx, xy, xz, yy,
+ * yz, zz (for L = 2; lexicographic in general); the global function order is
+ * shell order. Borrowed for the duration of the call only.
+ */
+typedef struct xc_basis {
+    int nshells;
+    const int* shell_atom;
+    const int* shell_L;
+    const int* shell_nprim;
+    const double* prim_alpha;   /* sum(nprim), > 0 */
+    const double* prim_coef;    /* sum(nprim) */
+} xc_basis;
+
+/*
+ * Grid specification (Sec. 2.2; Table 2 shapes; eq. rcut; batch threshold).
+ *  n_rad       radial points per atom, Mura-Knowles r = -alpha ln(1 - x^3)
+ *              on midpoint nodes x_k = (k - 1/2)/n_rad
+ *  n_ang       angular points per atom
+ *  ang_xyzw    n_ang x 4: unit vector and weight (weights sum to 4 pi)
+ *  ssf_a       Stratmann-Scuseria-Frisch cell parameter, 0 < a < 1 (0.64)
+ *  screen_eta  eq. rcut tolerance eta; 0 disables truncation and screening
+ *  batch_max   largest number of points in one batch, 16..1024 (512)
+ *  rho_thresh  points with rho below it add nothing to E_xc and V_xc
+ *  atom_mask   NULL, or natoms flags: only the grids of flagged parent atoms
+ *              are integrated (the partition still uses every atom)
+ */
+typedef struct xc_grid_spec {
+    int n_rad;
+    int n_ang;
+    const double* ang_xyzw;
+    double ssf_a;
+    double screen_eta;
+    int batch_max;
+    double rho_thresh;
+    const unsigned char* atom_mask;
+} xc_grid_spec;
+
+/*
+ * Device options for a context.
+ *  stream      hipStream_t every launch and copy of the context is ordered
+ *              on (NULL: the null stream). The library never changes stream
+ *              priorities.
+ *  wave_bytes  budget of device scratch for one wave of batches (the paper's
+ *              "saturate device memory" subsets, Alg. 2); 0 picks a default
+ *              from the free device memory.
+ */
+typedef struct xc_device_opts {
+    void* stream;
+    size_t wave_bytes;
+} xc_device_opts;
+
+/* Sizes of a built grid; all counts refer to the points actually integrated. */
+typedef struct xc_stats {
+    long long n_points_nominal;  /* masked atoms x n_rad x n_ang */
+    long long n_points;          /* points with non-zero weight */
+    long long n_batches;
+    long long n_shell_entries;   /* sum over batches of the screened shell count */
+    long long n_func_entries;    /* sum over batches of n_b */
+    int max_nb;
+    int max_ng;
+    double sum_nb_ng;            /* sum_j n_b^j n_g^j */
+    double sum_nb2_ng;           /* sum_j (n_b^j)^2 n_g^j */
+    double flops_contract;       /* algorithmic FP64 flops of the two contractions
+                                    per integration: sum_j 2 n_b^2 n_g + 2 n_b (n_b+1) n_g */
+    int n_waves;
+    int built;                   /* 1 once xc_context_build_grid has run */
+    size_t persistent_bytes;     /* device bytes held between integrations */
+    size_t wave_bytes;           /* device scratch bytes of the largest wave */
+} xc_stats;
+
+/*
+ * Per-phase device time, measured with HIP events recorded on the
+ * context's stream around each phase's launches (the component split of the
+ * paper's profile: weights, collocation, the two contractions, the
+ * functional, the rest). Phases:
+ */
+#define XC_PHASE_GRID       0   /* grid points */
+#define XC_PHASE_WEIGHTS    1   /* SSF partition weights */
+#define XC_PHASE_COMPACT    2   /* removal of zero-weight points */
+#define XC_PHASE_BATCH      3   /* cuboid batching */
+#define XC_PHASE_SCREEN     4   /* shell screening (Alg. 1) */
+#define XC_PHASE_COLLOC     5   /* collocation Phi, grad Phi */
+#define XC_PHASE_DENSITY    6   /* X = P Phi on MFMA with rho, grad rho epilogue */
+#define XC_PHASE_FUNCTIONAL 7   /* functional, E_xc/N_e partials, Z */
+#define XC_PHASE_POTENTIAL  8   /* V = Z Phi^T + Phi Z^T on MFMA with scatter-add */
+#define XC_PHASE_OTHER      9   /* zero fill, mirror, final sums */
+#define XC_NUM_PHASES      10
+
+typedef struct xc_timing {
+    double ms[XC_NUM_PHASES];          /* accumulated device milliseconds */
+    long long launches[XC_NUM_PHASES]; /* timed intervals (one per launch or phase) */
+} xc_timing;
+
+typedef struct xc_context xc_context;
+
+/* Static message for a return code. */
+const char* xc_strerror(int code);
+/* Message describing the calling thread's most recent error ("" if none). */
+const char* xc_last_error(void);
+/* XC_ABI_VERSION of the loaded library. */
+int xc_abi_version(void);
+
+/*
+ * One-shot integration with host buffers: builds the grid, integrates and
+ * releases every device resource before returning. P (nbf x nbf, symmetric)
+ * is read; V (nbf x nbf) is written in full and exactly symmetric; *E_xc and
+ * *N_e are written. nbf must equal the basis function count. Synchronous.
+ */
+int xc_integrate(const xc_molecule* mol, const xc_basis* basis,
+                 const xc_grid_spec* grid, int functional, int precision,
+                 const double* P, int nbf,
+                 double* E_xc, double* N_e, double* V);
+
+/*
+ * Create a context that keeps atoms, shells and (after build) the grid,
+ * weights, batches and screening lists on the device across integrations
+ * (grid reuse across Fock builds, Sec. 2.3.1). Inputs are copied; the caller
+ * keeps ownership of everything it passed. *out receives the new context.
+ */
+int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
+                      const xc_grid_spec* grid, const xc_device_opts* opts,
+                      xc_context** out);
+
+/*
+ * Build or rebuild the grid on the device (grid points, SSF weights, removal
+ * of zero-weight points, cuboid batching, shell screening by Alg. 1, wave
+ * plan). Synchronises the context's stream to learn sizes. A rebuild of an
+ * unchanged context reuses its allocations and gives the same batches.
+ */
+int xc_context_build_grid(xc_context* ctx);
+
+/*
+ * Integrate with device buffers, ordered on the context's stream and
+ * asynchronous with respect to the host (no synchronisation inside once the
+ * grid is built; builds it first otherwise).
+ *  d_P   nbf x nbf FP64 density matrix in device memory (read)
+ *  d_V   nbf x nbf FP64 in device memory (overwritten with V_xc)
+ *  d_EN  2 FP64 in device memory (overwritten with E_xc, N_e)
+ */
+int xc_context_integrate(xc_context* ctx, int functional, int precision,
+                         const double* d_P, double* d_V, double* d_EN);
+
+/* Sizes of the built grid (host struct, filled synchronously). */
+int xc_context_stats(xc_context* ctx, xc_stats* out);
+
+/*
+ * Copy the built grid to host arrays in batch order: xyzw (n_points x 4:
+ * point and SSF-scaled weight), index (n_points: position of the point in
+ * the unpruned masked-atom grid, atom-major, radial outer, angular inner).
+ * Synchronous. Either pointer may be NULL.
+ */
+int xc_context_export_grid(xc_context* ctx, double* xyzw, long long* index);
+
+/*
+ * Copy the batches to host arrays. point_ptr (n_batches + 1): first point of
+ * each batch in export_grid order; bbox (n_batches x 6: min xyz, max xyz);
+ * shell_ptr (n_batches + 1) and shells (n_shell_entries): the screened shell
+ * list of each batch, ascending. Synchronous. Any pointer may be NULL.
+ */
+int xc_context_export_batches(xc_context* ctx, long long* point_ptr,
+                              double* bbox, long long* shell_ptr, int* shells);
+
+/*
+ * Turn per-phase timing on (enable != 0) or off; either way the accumulated
+ * times are reset. While on, every launch is bracketed by two events on the
+ * context's stream.
+ */
+int xc_context_set_timing(xc_context* ctx, int enable);
+
+/* Accumulated per-phase times since the last reset (synchronises the stream). */
+int xc_context_timing(xc_context* ctx, xc_timing* out);
+
+/* Release every device resource of the context (synchronises its stream). */
+int xc_context_destroy(xc_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XC_MI355X_H */

@@ -25,20 +25,26 @@ def density_on_points(points, coords, basis, P, eta, grad=True):
     return rho, g, phi, dphi
 
 
-def grid_and_weights(coords, mk_alpha, n_rad, ang, ssf_a=0.64, atom_mask=None):
+def grid_and_weights(coords, mk_alpha, n_rad, ang, ssf_a=0.64, atom_mask=None,
+                     progress=None, point_slice=None):
     pts, wq, parent = molecular_grid(coords, mk_alpha, n_rad, ang, atom_mask)
-    w = ssf_weights(pts, wq, parent, coords, ssf_a)
+    if point_slice is not None:
+        pts, wq, parent = pts[point_slice], wq[point_slice], parent[point_slice]
+    w = ssf_weights(pts, wq, parent, coords, ssf_a, progress=progress)
     return pts, w, parent
 
 
 def integrate(coords, mk_alpha, basis, P, functional, n_rad, ang,
               ssf_a=0.64, screen_eta=1e-10, rho_thresh=1e-15, atom_mask=None,
-              chunk=None, details=False):
-    """Return (E_xc, N_e, V_xc) [and per-point details when asked]."""
+              chunk=None, details=False, progress=None, point_slice=None):
+    """Return (E_xc, N_e, V_xc) [and per-point details when asked].
+    progress(stage, done, total), if given, is called after every chunk;
+    point_slice, if given, restricts the sums to that slice of the grid
+    points (a sample of the work)."""
     coords = np.asarray(coords, dtype=np.float64)
     gga = functional == "pbe"
     pts, w, parent = grid_and_weights(coords, mk_alpha, n_rad, ang, ssf_a,
-                                      atom_mask)
+                                      atom_mask, progress, point_slice)
     nbf = basis.nbf
     if chunk is None:
         chunk = max(256, min(8192, int(2e7 // max(nbf, 1))))
@@ -60,6 +66,8 @@ def integrate(coords, mk_alpha, basis, P, functional, n_rad, ang,
                 c = 2.0 * wc * vs * g[d]
                 V += phi.T @ (dphi[d] * c[:, None])
                 V += dphi[d].T @ (phi * c[:, None])
+        if progress is not None:
+            progress("integrate", min(c0 + chunk, pts.shape[0]), pts.shape[0])
         if details:
             rho_all.append(rho)
             sig_all.append(sigma if gga else np.zeros_like(rho))

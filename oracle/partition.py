@@ -17,7 +17,11 @@ import numpy as np
 def ssf_cell(mu, a=0.64):
     """s(mu) of the SSF scheme, elementwise."""
     z = mu / a
-    g = (35.0 * z - 35.0 * z ** 3 + 21.0 * z ** 5 - 5.0 * z ** 7) / 16.0
+    z2 = z * z
+    z3 = z2 * z
+    z5 = z3 * z2
+    z7 = z5 * z2
+    g = (35.0 * z - 35.0 * z3 + 21.0 * z5 - 5.0 * z7) / 16.0
     g = np.where(mu <= -a, -1.0, np.where(mu >= a, 1.0, g))
     return 0.5 * (1.0 - g)
 
@@ -29,15 +33,13 @@ def ssf_partition(points, coords, a=0.64):
     R = np.linalg.norm(coords[:, None, :] - coords[None, :, :], axis=2)
     Pm = np.ones((points.shape[0], n_at))
     for A in range(n_at):
-        for B in range(n_at):
-            if A == B:
-                continue
-            mu = (d[:, A] - d[:, B]) / R[A, B]
-            Pm[:, A] *= ssf_cell(mu, a)
+        others = np.arange(n_at) != A
+        mu = (d[:, A:A + 1] - d[:, others]) / R[A, others][None, :]
+        Pm[:, A] = np.prod(ssf_cell(mu, a), axis=1)
     return Pm / Pm.sum(axis=1, keepdims=True)
 
 
-def ssf_weights(points, w_q, parent, coords, a=0.64, chunk=2048):
+def ssf_weights(points, w_q, parent, coords, a=0.64, chunk=2048, progress=None):
     """Scaled weights w_i = p_{A(i)}(r_i) w^q_i (eq. num_int)."""
     out = np.empty_like(w_q)
     if coords.shape[0] == 1:
@@ -47,4 +49,6 @@ def ssf_weights(points, w_q, parent, coords, a=0.64, chunk=2048):
         sl = slice(c0, c0 + chunk)
         p = ssf_partition(points[sl], coords, a)
         out[sl] = w_q[sl] * p[np.arange(p.shape[0]), parent[sl]]
+        if progress is not None:
+            progress("ssf", min(c0 + chunk, points.shape[0]), points.shape[0])
     return out

@@ -1,0 +1,77 @@
+// Small device helpers: block scans and reductions, launch geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace xc {
+
+// Exclusive scan of one int per thread across the block (blockDim.x a
+// multiple of 64, at most 1024). smem needs 17 ints. Every thread receives
+// the block total.
+__device__ inline int block_exclusive_scan(int v, int* smem, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) smem[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < nw; ++w) {
+            int t = smem[w];
+            smem[w] = run;
+            run += t;
+        }
+        smem[nw] = run;
+    }
+    __syncthreads();
+    int excl = smem[wid] + x - v;
+    total = smem[nw];
+    __syncthreads();
+    return excl;
+}
+
+// Sum of one double per thread across a 256-thread block in a fixed order
+// (the same tree every run). smem needs 256 doubles. Result valid in thread 0.
+__device__ inline double block_sum_256(double v, double* smem) {
+    smem[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) smem[threadIdx.x] += smem[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = smem[0];
+    __syncthreads();
+    return r;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; this maps the
+// hardware block id to a logical id so that consecutive logical ids run on
+// the same XCD and share its L2.
+__device__ inline int xcd_remap(int bid, int nblk) {
+    const int xcd = bid & 7, idx = bid >> 3;
+    const int base = nblk >> 3, rem = nblk & 7;
+    return (xcd < rem) ? xcd * (base + 1) + idx
+                       : rem * (base + 1) + (xcd - rem) * base + idx;
+}
+
+// Largest b in [0, n) with prefix[b] <= t (prefix ascending, prefix[0] = 0).
+__device__ inline int find_segment(const int* prefix, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+inline unsigned grid_1d(long long n, int block) {
+    return (unsigned)((n + block - 1) / block);
+}
+
+}  // namespace xc

@@ -1,0 +1,293 @@
+// Grid construction on the device: shell cutoff radii (eq. rcut), the
+// Mura-Knowles x Lebedev product grid of every parent atom (Sec. 2.2,
+// eq. num_int), Stratmann-Scuseria-Frisch partition weights (eq.
+// atomic_partition), and stable removal of zero-weight points.
+#include <cmath>
+
+#include "device_util.hpp"
+#include "xc_internal.hpp"
+
+namespace xc {
+
+// ---------------------------------------------------------------- rcut ----
+// r_cut = max over primitives of sqrt((ln(alpha)/2 - ln(eta)) / alpha);
+// eta <= 0 disables truncation (rcut2 = +inf).
+__global__ void k_shell_rcut(ShellDev* sh, int nshells, const double* alpha,
+                             double eta) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nshells) return;
+    ShellDev d = sh[s];
+    if (!(eta > 0.0)) {
+        sh[s].rcut2 = INFINITY;
+        return;
+    }
+    const double leta = log(eta);
+    double rc = 0.0;
+    for (int p = 0; p < d.nprim; ++p) {
+        const double a = alpha[d.prim_off + p];
+        double arg = (0.5 * log(a) - leta) / a;
+        rc = fmax(rc, sqrt(fmax(arg, 0.0)));
+    }
+    sh[s].rcut2 = rc * rc;
+}
+
+// inverse inter-atomic distances and the nearest-neighbour shortcut radius
+// (1 - a)/2 * min_B R_AB of every atom
+__global__ void k_atom_pairs(const double4* atoms, int natoms, double a,
+                             double* invR, double* nnhalf) {
+    int A = blockIdx.x * blockDim.x + threadIdx.x;
+    if (A >= natoms) return;
+    const double4 ra = atoms[A];
+    double rmin = INFINITY;
+    for (int B = 0; B < natoms; ++B) {
+        if (B == A) {
+            invR[(size_t)A * natoms + B] = 0.0;
+            continue;
+        }
+        const double4 rb = atoms[B];
+        const double dx = ra.x - rb.x, dy = ra.y - rb.y, dz = ra.z - rb.z;
+        const double R = sqrt(dx * dx + dy * dy + dz * dz);
+        invR[(size_t)A * natoms + B] = 1.0 / R;
+        rmin = fmin(rmin, R);
+    }
+    nnhalf[A] = 0.5 * (1.0 - a) * rmin;
+}
+
+int launch_shell_setup(xc_context* c) {
+    hipLaunchKernelGGL(k_shell_rcut, dim3(grid_1d(c->nshells, 128)), dim3(128), 0,
+                       c->stream, (ShellDev*)c->d_shells.p, c->nshells,
+                       (const double*)c->d_palpha.p, c->screen_eta);
+    XC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_atom_pairs, dim3(grid_1d(c->natoms, 128)), dim3(128), 0,
+                       c->stream, (const double4*)c->d_atoms.p, c->natoms, c->ssf_a,
+                       (double*)c->d_invR.p, (double*)c->d_nnhalf.p);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
+// ---------------------------------------------------------- grid points ---
+// Point i of masked atom g: radial index k (outer), angular index l (inner).
+// r_k = -alpha ln(1 - x_k^3), x_k = (k + 1/2)/n_rad, weight
+// (3 alpha x_k^2 / (1 - x_k^3)) / n_rad * r_k^2 * w_l.
+__global__ void k_grid_points(long long n, int npa, int n_rad, int n_ang,
+                              const int* gatoms, const double4* atoms,
+                              const double4* ang, double* X, double* Y,
+                              double* Z, double* W) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int g = (int)(i / npa);
+    const int rem = (int)(i - (long long)g * npa);
+    const int k = rem / n_ang, l = rem - k * n_ang;
+    const double4 at = atoms[gatoms[g]];
+    const double alpha = at.w;
+    const double xk = (k + 0.5) / n_rad;
+    const double om = 1.0 - xk * xk * xk;
+    const double r = -alpha * log(om);
+    const double wr = (3.0 * alpha * xk * xk / om) / n_rad * r * r;
+    const double4 s = ang[l];
+    X[i] = at.x + r * s.x;
+    Y[i] = at.y + r * s.y;
+    Z[i] = at.z + r * s.z;
+    W[i] = wr * s.w;
+}
+
+int launch_grid_points(xc_context* c) {
+    PhaseScope ps(c, XC_PHASE_GRID);
+    const int npa = c->n_rad * c->n_ang;
+    hipLaunchKernelGGL(k_grid_points, dim3(grid_1d(c->n_nominal, 256)), dim3(256), 0,
+                       c->stream, c->n_nominal, npa, c->n_rad, c->n_ang,
+                       (const int*)c->d_gatoms.p, (const double4*)c->d_atoms.p,
+                       (const double4*)c->d_ang.p, (double*)c->raw_x.p,
+                       (double*)c->raw_y.p, (double*)c->raw_z.p, (double*)c->raw_w.p);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
+// ------------------------------------------------------------------ SSF ---
+// s(mu) = (1 - g(mu))/2 with g the SSF polynomial on |mu| < a, +-1 outside.
+__device__ inline double ssf_s(double mu, double a) {
+    if (mu <= -a) return 1.0;
+    if (mu >= a) return 0.0;
+    const double z = mu / a, z2 = z * z;
+    const double g = z * (35.0 + z2 * (-35.0 + z2 * (21.0 - 5.0 * z2))) * 0.0625;
+    return 0.5 * (1.0 - g);
+}
+
+__device__ inline double dist_to(const double4& at, double x, double y, double z) {
+    const double dx = x - at.x, dy = y - at.y, dz = z - at.z;
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// Unnormalised cell product P_C(r) = prod_{B != C} s(mu_CB); stops at zero.
+__device__ inline double ssf_product(int C, double dC, const double4* atoms,
+                                     const double* invR, int natoms, double x,
+                                     double y, double z, double a) {
+    double p = 1.0;
+    const double* ir = invR + (size_t)C * natoms;
+    for (int B = 0; B < natoms; ++B) {
+        if (B == C) continue;
+        const double dB = dist_to(atoms[B], x, y, z);
+        p *= ssf_s((dC - dB) * ir[B], a);
+        if (p == 0.0) break;
+    }
+    return p;
+}
+
+// w_i <- w_i * P_parent / sum_C P_C. Exact reductions of the work:
+//  * |r - R_A| < (1-a)/2 min_B R_AB: the parent owns the point (p = 1);
+//  * an atom C with (d_C - d_min) / R_{C,nearest} >= a has s(mu_{C,nearest}) = 0,
+//    hence P_C = 0, and is skipped.
+__global__ void k_ssf(long long n, int npa, const int* gatoms, const double4* atoms,
+                      const double* invR, const double* nnhalf, int natoms,
+                      double a, const double* X, const double* Y, const double* Z,
+                      double* W) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double w = W[i];
+    if (w == 0.0 || natoms == 1) return;
+    const int A = gatoms[(int)(i / npa)];
+    const double x = X[i], y = Y[i], z = Z[i];
+    const double dA = dist_to(atoms[A], x, y, z);
+    if (dA < nnhalf[A]) return;
+    double dmin = INFINITY;
+    int bmin = 0;
+    for (int B = 0; B < natoms; ++B) {
+        const double d = dist_to(atoms[B], x, y, z);
+        if (d < dmin) {
+            dmin = d;
+            bmin = B;
+        }
+    }
+    const double PA = ssf_product(A, dA, atoms, invR, natoms, x, y, z, a);
+    if (PA == 0.0) {
+        W[i] = 0.0;
+        return;
+    }
+    double sum = 0.0;
+    for (int C = 0; C < natoms; ++C) {
+        if (C == A) {
+            sum += PA;
+            continue;
+        }
+        const double dC = dist_to(atoms[C], x, y, z);
+        if (C != bmin && (dC - dmin) * invR[(size_t)C * natoms + bmin] >= a) continue;
+        sum += ssf_product(C, dC, atoms, invR, natoms, x, y, z, a);
+    }
+    W[i] = w * (PA / sum);
+}
+
+int launch_ssf(xc_context* c) {
+    PhaseScope ps(c, XC_PHASE_WEIGHTS);
+    const int npa = c->n_rad * c->n_ang;
+    hipLaunchKernelGGL(k_ssf, dim3(grid_1d(c->n_nominal, 256)), dim3(256), 0, c->stream,
+                       c->n_nominal, npa, (const int*)c->d_gatoms.p,
+                       (const double4*)c->d_atoms.p, (const double*)c->d_invR.p,
+                       (const double*)c->d_nnhalf.p, c->natoms, c->ssf_a,
+                       (const double*)c->raw_x.p, (const double*)c->raw_y.p,
+                       (const double*)c->raw_z.p, (double*)c->raw_w.p);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
+// ------------------------------------------------------------ compaction --
+// Blocks of kCompactSpan points, aligned to each atom's segment, count their
+// non-zero weights; a second pass writes the kept points in order.
+constexpr int kCompactSpan = 1024;
+
+__global__ void k_compact_count(const double* W, int npa, int nblk_atom, int* count) {
+    const int g = blockIdx.x / nblk_atom, kb = blockIdx.x - g * nblk_atom;
+    const long long base = (long long)g * npa + (long long)kb * kCompactSpan;
+    const int len = min(kCompactSpan, npa - kb * kCompactSpan);
+    int c = 0;
+    for (int j = threadIdx.x; j < len; j += blockDim.x) c += (W[base + j] != 0.0);
+    __shared__ int red[256];
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count[blockIdx.x] = red[0];
+}
+
+__global__ void k_compact_write(const double* X, const double* Y, const double* Z,
+                                const double* W, int npa, int nblk_atom,
+                                const long long* off, double* ox, double* oy,
+                                double* oz, double* ow, long long* oidx) {
+    const int g = blockIdx.x / nblk_atom, kb = blockIdx.x - g * nblk_atom;
+    const long long base = (long long)g * npa + (long long)kb * kCompactSpan;
+    const int len = min(kCompactSpan, npa - kb * kCompactSpan);
+    // 256 threads x 4 consecutive points each
+    const int j0 = threadIdx.x * 4;
+    int keep[4];
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q;
+        keep[q] = (j < len) && (W[base + j] != 0.0);
+        c += keep[q];
+    }
+    __shared__ int smem[17];
+    int total;
+    int pos = block_exclusive_scan(c, smem, total);
+    long long dst = off[blockIdx.x] + pos;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!keep[q]) continue;
+        const long long s = base + j0 + q;
+        ox[dst] = X[s];
+        oy[dst] = Y[s];
+        oz[dst] = Z[s];
+        ow[dst] = W[s];
+        oidx[dst] = s;
+        ++dst;
+    }
+}
+
+int launch_compact(xc_context* c, std::vector<long long>& atom_kept) {
+    PhaseScope ps(c, XC_PHASE_COMPACT);
+    const int npa = c->n_rad * c->n_ang;
+    const int nblk_atom = (npa + kCompactSpan - 1) / kCompactSpan;
+    const int nga = (int)c->gatoms.size();
+    const int nblk = nga * nblk_atom;
+    XC_TRY(dev_reserve(c->blk_count, sizeof(int) * (size_t)nblk));
+    XC_TRY(dev_reserve(c->blk_off, sizeof(long long) * (size_t)nblk));
+    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(256), 0, c->stream,
+                       (const double*)c->raw_w.p, npa, nblk_atom, (int*)c->blk_count.p);
+    XC_HIP(hipGetLastError());
+    std::vector<int> cnt(nblk);
+    XC_HIP(hipMemcpyAsync(cnt.data(), c->blk_count.p, sizeof(int) * (size_t)nblk,
+                          hipMemcpyDeviceToHost, c->stream));
+    XC_HIP(hipStreamSynchronize(c->stream));
+    std::vector<long long> off(nblk);
+    atom_kept.assign(nga, 0);
+    long long run = 0;
+    for (int b = 0; b < nblk; ++b) {
+        off[b] = run;
+        run += cnt[b];
+        atom_kept[b / nblk_atom] += cnt[b];
+    }
+    c->n_points = run;
+    XC_TRY(upload(c->blk_off, off.data(), sizeof(long long) * (size_t)nblk, c->stream));
+    const size_t np = (size_t)(run > 0 ? run : 1);
+    XC_TRY(dev_reserve(c->px, 8 * np));
+    XC_TRY(dev_reserve(c->py, 8 * np));
+    XC_TRY(dev_reserve(c->pz, 8 * np));
+    XC_TRY(dev_reserve(c->pw, 8 * np));
+    XC_TRY(dev_reserve(c->pidx, 8 * np));
+    XC_TRY(dev_reserve(c->tx, 8 * np));
+    XC_TRY(dev_reserve(c->ty, 8 * np));
+    XC_TRY(dev_reserve(c->tz, 8 * np));
+    XC_TRY(dev_reserve(c->tw, 8 * np));
+    XC_TRY(dev_reserve(c->tidx, 8 * np));
+    hipLaunchKernelGGL(k_compact_write, dim3(nblk), dim3(256), 0, c->stream,
+                       (const double*)c->raw_x.p, (const double*)c->raw_y.p,
+                       (const double*)c->raw_z.p, (const double*)c->raw_w.p, npa,
+                       nblk_atom, (const long long*)c->blk_off.p, (double*)c->px.p,
+                       (double*)c->py.p, (double*)c->pz.p, (double*)c->pw.p,
+                       (long long*)c->pidx.p);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
+}  // namespace xc

@@ -1,0 +1,599 @@
+// Per-wave integration kernels (Sec. 2.2 eq. eval_local_den, eq.
+// eval_local_den_grad, eq. x_mat, eq. exc_batch, eq. vxc_inc, eq. vxc_batch,
+// eq. z_mat; Sec. 2.3.2 Alg. 4).
+//
+// For every batch j of a wave, in four launches over all its batches:
+//  1. collocation  Phi^j (n_b x n_g) and, for the GGA, grad Phi^j, written in
+//     compressed form over the screened functions;
+//  2. X = P^j Phi^j on FP64 MFMA with P^j gathered straight from the full
+//     P (never packed), and rho, grad rho reduced from X in the epilogue
+//     (X is never stored);
+//  3. the functional per point, the batch's E_xc and N_e partials, and
+//     Z^j = (1/2) w v_rho Phi + 2 w v_sigma grad rho . grad Phi;
+//  4. V^j = Z Phi^T + Phi Z^T on FP64 MFMA over lower-triangle tiles only,
+//     added into the lower triangle of the full V with FP64 atomics.
+// Then V is mirrored and E_xc, N_e are summed in a fixed order.
+#include <cmath>
+
+#include "device_util.hpp"
+#include "functional.hpp"
+#include "xc_internal.hpp"
+
+namespace xc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------ collocation --
+// Values (and gradients) of the (L+1)(L+2)/2 Cartesian functions of one
+// shell at one point, written down the rows starting at out (row stride ngp;
+// gradients at +slab, +2 slab, +3 slab).
+template <int L, bool GGA>
+__device__ inline void colloc_shell(double dx, double dy, double dz, double rad,
+                                    double drad, bool live, double* out, int ngp,
+                                    size_t slab) {
+    double xp[L + 1], yp[L + 1], zp[L + 1];
+    xp[0] = yp[0] = zp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        xp[k] = xp[k - 1] * dx;
+        yp[k] = yp[k - 1] * dy;
+        zp[k] = zp[k - 1] * dz;
+    }
+    int c = 0;
+#pragma unroll
+    for (int l = L; l >= 0; --l) {
+#pragma unroll
+        for (int m = L - l; m >= 0; --m) {
+            const int n = L - l - m;
+            double* o = out + (size_t)c * ngp;
+            if (!live) {
+                o[0] = 0.0;
+                if (GGA) {
+                    o[slab] = 0.0;
+                    o[2 * slab] = 0.0;
+                    o[3 * slab] = 0.0;
+                }
+            } else {
+                const double ang = xp[l] * yp[m] * zp[n];
+                o[0] = ang * rad;
+                if (GGA) {
+                    const double ad = ang * drad;
+                    const double gx = (l ? l * xp[l - 1] * yp[m] * zp[n] : 0.0);
+                    const double gy = (m ? m * xp[l] * yp[m - 1] * zp[n] : 0.0);
+                    const double gz = (n ? n * xp[l] * yp[m] * zp[n - 1] : 0.0);
+                    o[slab] = gx * rad + ad * dx;
+                    o[2 * slab] = gy * rad + ad * dy;
+                    o[3 * slab] = gz * rad + ad * dz;
+                }
+            }
+            ++c;
+        }
+    }
+}
+
+// One workgroup per batch; wave w evaluates shells w, w+4, ... of the
+// batch's screened list, one lane per point, so a wave never diverges on
+// the contraction length. Points of the batch are staged in LDS.
+template <bool GGA>
+__global__ __launch_bounds__(256) void k_colloc(
+    const WaveBatch* __restrict__ wb, const ShellDev* __restrict__ shells,
+    const double* __restrict__ palpha, const double* __restrict__ pcoef,
+    const int* __restrict__ shell_list, const int* __restrict__ shell_loff,
+    const double* __restrict__ X, const double* __restrict__ Y,
+    const double* __restrict__ Z, double* __restrict__ scratch) {
+    const WaveBatch B = wb[blockIdx.x];
+    __shared__ double sx[kMaxBatch], sy[kMaxBatch], sz[kMaxBatch];
+    for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
+        const bool v = i < B.ng;
+        sx[i] = v ? X[B.pt_off + i] : 0.0;
+        sy[i] = v ? Y[B.pt_off + i] : 0.0;
+        sz[i] = v ? Z[B.pt_off + i] : 0.0;
+    }
+    __syncthreads();
+    double* Phi = scratch + B.phi_off;
+    const size_t slab = (size_t)B.nbp * B.ngp;
+    // zero the padding rows n_b .. n_bp - 1
+    const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
+    for (long long k = threadIdx.x; k < npad; k += blockDim.x) {
+        const size_t off = (size_t)B.nb * B.ngp + k;
+        Phi[off] = 0.0;
+        if (GGA) {
+            Phi[slab + off] = 0.0;
+            Phi[2 * slab + off] = 0.0;
+            Phi[3 * slab + off] = 0.0;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int sl = wave; sl < B.nshell; sl += 4) {
+        const int s = shell_list[B.shell_off + sl];
+        const int loff = shell_loff[B.shell_off + sl];
+        const ShellDev sh = shells[s];
+        for (int i = lane; i < B.ngp; i += 64) {
+            double dx, dy, dz, r2;
+            {
+#pragma clang fp contract(off)
+                dx = sx[i] - sh.x;
+                dy = sy[i] - sh.y;
+                dz = sz[i] - sh.z;
+                r2 = dx * dx + dy * dy + dz * dz;
+            }
+            const bool live = (i < B.ng) && (r2 <= sh.rcut2);
+            double rad = 0.0, drad = 0.0;
+            if (live) {
+                for (int p = 0; p < sh.nprim; ++p) {
+                    const double a = palpha[sh.prim_off + p];
+                    const double de = pcoef[sh.prim_off + p] * exp(-a * r2);
+                    rad += de;
+                    drad -= 2.0 * a * de;
+                }
+            }
+            double* out = Phi + (size_t)loff * B.ngp + i;
+            switch (sh.L) {
+                case 0: colloc_shell<0, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
+                case 1: colloc_shell<1, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
+                case 2: colloc_shell<2, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
+                default: colloc_shell<3, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- density (GEMM) ----
+// Tile of 64 functions x 64 points of X = P^j Phi^j; 4 waves, each a 32 x 32
+// block of 2 x 2 MFMA 16x16x4 FP64 tiles. A operand rows are gathered from
+// the full P through the batch's function list. The epilogue reduces
+// Phi*X (and grad Phi * X) over the tile's rows into per-row-tile partials
+// part[mt][q][point], q = rho, dx, dy, dz.
+template <bool GGA>
+__global__ __launch_bounds__(256) void k_gemm_rho(
+    const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
+    int ntiles, const double* __restrict__ P, int nbf,
+    const int* __restrict__ func_list, double* __restrict__ scratch) {
+    const int t = xcd_remap(blockIdx.x, ntiles);
+    const int bi = find_segment(prefix, nwb, t);
+    const WaveBatch B = wb[bi];
+    const int lt = t - prefix[bi];
+    const int ntn = B.ngp / kTile;
+    const int mt = lt / ntn, nt = lt - mt * ntn;
+    const int m0 = mt * kTile, n0 = nt * kTile;
+    const size_t slab = (size_t)B.nbp * B.ngp;
+    const double* Phi = scratch + B.phi_off;
+    const int* fl = func_list + B.func_off;
+
+    __shared__ double As[2][kTile][17];
+    __shared__ double Bs[2][16][kTile + 1];
+    __shared__ int frow[kTile];
+    __shared__ double red[4][kTile];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    if (tid < kTile) frow[tid] = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
+    __syncthreads();
+
+    const int ar = tid >> 2, ac = (tid & 3) * 4;
+    const int br = tid >> 4, bc = (tid & 15) * 4;
+    const int fr = frow[ar];
+    const double* Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
+
+    double ra[4], rb[4];
+    auto gload = [&](int ks) {
+        const int k0 = ks * 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = k0 + ac + q;
+            ra[q] = (fr >= 0 && kk < B.nb) ? Prow[fl[kk]] : 0.0;
+        }
+        const double* src = Phi + (size_t)(k0 + br) * B.ngp + n0 + bc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rb[q] = src[q];
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[buf][ar][ac + q] = ra[q];
+            Bs[buf][br][bc + q] = rb[q];
+        }
+    };
+
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = B.nbp / 16;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ks = 0; ks < nk; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < nk) gload(ks + 1);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            double a[2], b[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+                a[mb] = As[cur][wm * 32 + mb * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+                b[nb] = Bs[cur][kk * 4 + (lane >> 4)][wn * 32 + nb * 16 + (lane & 15)];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma64(a[mb], b[nb], acc[mb][nb]);
+        }
+        if (ks + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    constexpr int NQ = GGA ? 4 : 1;
+    double q[NQ][2];
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) q[qq][0] = q[qq][1] = 0.0;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = m0 + wm * 32 + mb * 16 + 4 * r + (lane >> 4);
+            if (row < B.nb) {
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    const int col = n0 + wn * 32 + nb * 16 + (lane & 15);
+                    const double x = acc[mb][nb][r];
+                    const size_t off = (size_t)row * B.ngp + col;
+                    q[0][nb] += Phi[off] * x;
+                    if (GGA) {
+                        q[1 % NQ][nb] += Phi[slab + off] * x;
+                        q[2 % NQ][nb] += Phi[2 * slab + off] * x;
+                        q[3 % NQ][nb] += Phi[3 * slab + off] * x;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            double v = q[qq][nb];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            q[qq][nb] = v;
+        }
+    if (wm == 1 && lane < 16) {
+#pragma unroll
+        for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) red[qq][wn * 32 + nb * 16 + lane] = q[qq][nb];
+    }
+    __syncthreads();
+    if (wm == 0 && lane < 16) {
+        double* part = scratch + B.part_off;
+#pragma unroll
+        for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int ct = wn * 32 + nb * 16 + lane;
+                part[(size_t)(mt * 4 + qq) * B.ngp + n0 + ct] = q[qq][nb] + red[qq][ct];
+            }
+    }
+}
+
+// ------------------------------------------------- functional + Z matrix --
+template <bool GGA>
+__global__ __launch_bounds__(256) void k_func_z(
+    const WaveBatch* __restrict__ wb, const double* __restrict__ W, double rho_thresh,
+    double* __restrict__ scratch, double* __restrict__ epart,
+    double* __restrict__ npart) {
+    const WaveBatch B = wb[blockIdx.x];
+    __shared__ double sa[kMaxBatch], sbx[kMaxBatch], sby[kMaxBatch], sbz[kMaxBatch];
+    __shared__ double red[256];
+    const double* part = scratch + B.part_off;
+    double eacc = 0.0, nacc = 0.0;
+    for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
+        double a = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+        if (i < B.ng) {
+            double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+            for (int mt = 0; mt < B.nmt; ++mt) {
+                const double* p = part + (size_t)mt * 4 * B.ngp + i;
+                rho += p[0];
+                if (GGA) {
+                    gx += p[B.ngp];
+                    gy += p[2 * B.ngp];
+                    gz += p[3 * B.ngp];
+                }
+            }
+            const double w = W[B.pt_off + i];
+            nacc += w * rho;
+            if (rho >= rho_thresh) {
+                if (GGA) {
+                    gx *= 2.0;
+                    gy *= 2.0;
+                    gz *= 2.0;
+                    const double sigma = gx * gx + gy * gy + gz * gz;
+                    double e, vr, vs;
+                    fn::gga_pbe(rho, sigma, e, vr, vs);
+                    eacc += w * e;
+                    a = 0.5 * w * vr;
+                    const double f = 2.0 * w * vs;
+                    bx = f * gx;
+                    by = f * gy;
+                    bz = f * gz;
+                } else {
+                    double e, vr;
+                    fn::lda_svwn5(rho, e, vr);
+                    eacc += w * e;
+                    a = 0.5 * w * vr;
+                }
+            }
+        }
+        sa[i] = a;
+        if (GGA) {
+            sbx[i] = bx;
+            sby[i] = by;
+            sbz[i] = bz;
+        }
+    }
+    const double es = block_sum_256(eacc, red);
+    const double ns = block_sum_256(nacc, red);
+    if (threadIdx.x == 0) {
+        epart[B.batch] = es;
+        npart[B.batch] = ns;
+    }
+    // Z overwrites slab 1 (the x-gradient for the GGA, which is read first)
+    double* Phi = scratch + B.phi_off;
+    const size_t slab = (size_t)B.nbp * B.ngp;
+    double* Zm = Phi + slab;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int row = wave; row < B.nbp; row += 4) {
+        const size_t ro = (size_t)row * B.ngp;
+        for (int i = lane; i < B.ngp; i += 64) {
+            const size_t off = ro + i;
+            double z = sa[i] * Phi[off];
+            if (GGA) z += sbx[i] * Zm[off] + sby[i] * Phi[2 * slab + off] + sbz[i] * Phi[3 * slab + off];
+            Zm[off] = z;
+        }
+    }
+}
+
+// ------------------------------------------------------ potential (SYR2K) --
+// Lower-triangle tile (I >= J) of V^j = Z Phi^T + Phi Z^T, 64 x 64, over all
+// points of the batch, added into V[f(row)][f(col)] (f ascending, so the
+// global entry is in the lower triangle too).
+__global__ __launch_bounds__(256) void k_syr2k(
+    const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
+    int ntiles, const int* __restrict__ func_list, const double* __restrict__ scratch,
+    double* __restrict__ V, int nbf) {
+    const int t = xcd_remap(blockIdx.x, ntiles);
+    const int bi = find_segment(prefix, nwb, t);
+    const WaveBatch B = wb[bi];
+    const int lt = t - prefix[bi];
+    int I = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= lt) ++I;
+    while (I * (I + 1) / 2 > lt) --I;
+    const int J = lt - I * (I + 1) / 2;
+    const size_t slab = (size_t)B.nbp * B.ngp;
+    const double* Phi = scratch + B.phi_off;
+    const double* Zm = Phi + slab;
+    const int* fl = func_list + B.func_off;
+
+    __shared__ double sZI[2][kTile][17], sPI[2][kTile][17];
+    __shared__ double sPJ[2][kTile][17], sZJ[2][kTile][17];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = tid >> 2, lc = (tid & 3) * 4;
+    const int rI = I * kTile + lr, rJ = J * kTile + lr;
+    const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
+    const double* zI = Zm + (size_t)(vI ? rI : 0) * B.ngp;
+    const double* pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
+    const double* zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
+    const double* pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
+
+    double g[4][4];
+    auto gload = [&](int ks) {
+        const int k0 = ks * 16 + lc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            g[0][q] = vI ? zI[k0 + q] : 0.0;
+            g[1][q] = vI ? pI[k0 + q] : 0.0;
+            g[2][q] = vJ ? pJ[k0 + q] : 0.0;
+            g[3][q] = vJ ? zJ[k0 + q] : 0.0;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sZI[buf][lr][lc + q] = g[0][q];
+            sPI[buf][lr][lc + q] = g[1][q];
+            sPJ[buf][lr][lc + q] = g[2][q];
+            sZJ[buf][lr][lc + q] = g[3][q];
+        }
+    };
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = B.ngp / 16;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ks = 0; ks < nk; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < nk) gload(ks + 1);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int kc = kk * 4 + (lane >> 4);
+            double az[2], ap[2], bp[2], bz[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const int r = wm * 32 + mb * 16 + (lane & 15);
+                az[mb] = sZI[cur][r][kc];
+                ap[mb] = sPI[cur][r][kc];
+            }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int r = wn * 32 + nb * 16 + (lane & 15);
+                bp[nb] = sPJ[cur][r][kc];
+                bz[nb] = sZJ[cur][r][kc];
+            }
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    acc[mb][nb] = mfma64(az[mb], bp[nb], acc[mb][nb]);
+                    acc[mb][nb] = mfma64(ap[mb], bz[nb], acc[mb][nb]);
+                }
+        }
+        if (ks + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = I * kTile + wm * 32 + mb * 16 + 4 * r + (lane >> 4);
+            if (row >= B.nb) continue;
+            double* vrow = V + (size_t)fl[row] * nbf;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int col = J * kTile + wn * 32 + nb * 16 + (lane & 15);
+                if (col < B.nb && col <= row) unsafeAtomicAdd(vrow + fl[col], acc[mb][nb][r]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- misc ----
+__global__ void k_fill(double* p, long long n, double v) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// upper triangle <- lower triangle
+__global__ void k_mirror(double* V, int n) {
+    const int c = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int r = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (r < n && c < n && c > r) V[(size_t)r * n + c] = V[(size_t)c * n + r];
+}
+
+// E_xc and N_e from the per-batch partials: Neumaier-compensated sums in a
+// fixed order (one workgroup), so the result does not depend on timing.
+__device__ inline void two_sum_add(double& s, double& c, double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+__global__ void k_reduce_en(const double* epart, const double* npart, long long n,
+                            double* out) {
+    __shared__ double ss[2][256], cc[2][256];
+    double se = 0.0, ce = 0.0, sn = 0.0, cn = 0.0;
+    for (long long j = threadIdx.x; j < n; j += blockDim.x) {
+        two_sum_add(se, ce, epart[j]);
+        two_sum_add(sn, cn, npart[j]);
+    }
+    ss[0][threadIdx.x] = se;
+    cc[0][threadIdx.x] = ce;
+    ss[1][threadIdx.x] = sn;
+    cc[1][threadIdx.x] = cn;
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int k = threadIdx.x;
+        double s = 0.0, c = 0.0;
+        for (int i = 0; i < 256; ++i) {
+            two_sum_add(s, c, ss[k][i]);
+            c += cc[k][i];
+        }
+        out[k] = s + c;
+    }
+}
+
+// ------------------------------------------------------------- driver -----
+int run_integrate(xc_context* c, int functional, const double* dP, double* dV,
+                  double* dEN) {
+    const bool gga = functional == XC_GGA_PBE;
+    const long long nn = (long long)c->nbf * c->nbf;
+    {
+        PhaseScope ps(c, XC_PHASE_OTHER);
+        hipLaunchKernelGGL(k_fill, dim3(grid_1d(nn, 256)), dim3(256), 0, c->stream, dV, nn, 0.0);
+        XC_HIP(hipGetLastError());
+    }
+    const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
+    const int* gpre = (const int*)c->d_gemm_pre.p;
+    const int* spre = (const int*)c->d_syr_pre.p;
+    double* scr = (double*)c->scratch.p;
+    for (const Wave& w : c->waves) {
+        if (w.count == 0) continue;
+        const WaveBatch* b = wb + w.wb_off;
+        {
+        PhaseScope ps(c, XC_PHASE_COLLOC);
+        if (gga)
+            hipLaunchKernelGGL(k_colloc<true>, dim3(w.count), dim3(256), 0, c->stream, b,
+                               (const ShellDev*)c->d_shells.p, (const double*)c->d_palpha.p,
+                               (const double*)c->d_pcoef.p, (const int*)c->shell_list.p,
+                               (const int*)c->shell_loff.p, (const double*)c->px.p,
+                               (const double*)c->py.p, (const double*)c->pz.p, scr);
+        else
+            hipLaunchKernelGGL(k_colloc<false>, dim3(w.count), dim3(256), 0, c->stream, b,
+                               (const ShellDev*)c->d_shells.p, (const double*)c->d_palpha.p,
+                               (const double*)c->d_pcoef.p, (const int*)c->shell_list.p,
+                               (const int*)c->shell_loff.p, (const double*)c->px.p,
+                               (const double*)c->py.p, (const double*)c->pz.p, scr);
+        XC_HIP(hipGetLastError());
+        }
+        if (w.gemm_tiles > 0) {
+            PhaseScope ps(c, XC_PHASE_DENSITY);
+            if (gga)
+                hipLaunchKernelGGL(k_gemm_rho<true>, dim3(w.gemm_tiles), dim3(256), 0,
+                                   c->stream, b, gpre + w.pre_off, w.count, w.gemm_tiles,
+                                   dP, c->nbf, (const int*)c->func_list.p, scr);
+            else
+                hipLaunchKernelGGL(k_gemm_rho<false>, dim3(w.gemm_tiles), dim3(256), 0,
+                                   c->stream, b, gpre + w.pre_off, w.count, w.gemm_tiles,
+                                   dP, c->nbf, (const int*)c->func_list.p, scr);
+            XC_HIP(hipGetLastError());
+        }
+        {
+        PhaseScope ps(c, XC_PHASE_FUNCTIONAL);
+        if (gga)
+            hipLaunchKernelGGL(k_func_z<true>, dim3(w.count), dim3(256), 0, c->stream, b,
+                               (const double*)c->pw.p, c->rho_thresh, scr,
+                               (double*)c->epart.p, (double*)c->npart.p);
+        else
+            hipLaunchKernelGGL(k_func_z<false>, dim3(w.count), dim3(256), 0, c->stream, b,
+                               (const double*)c->pw.p, c->rho_thresh, scr,
+                               (double*)c->epart.p, (double*)c->npart.p);
+        XC_HIP(hipGetLastError());
+        }
+        if (w.syr_tiles > 0) {
+            PhaseScope ps(c, XC_PHASE_POTENTIAL);
+            hipLaunchKernelGGL(k_syr2k, dim3(w.syr_tiles), dim3(256), 0, c->stream, b,
+                               spre + w.pre_off, w.count, w.syr_tiles,
+                               (const int*)c->func_list.p, (const double*)scr, dV, c->nbf);
+            XC_HIP(hipGetLastError());
+        }
+    }
+    PhaseScope ps(c, XC_PHASE_OTHER);
+    const unsigned nt = (unsigned)((c->nbf + 15) / 16);
+    hipLaunchKernelGGL(k_mirror, dim3(nt, nt), dim3(256), 0, c->stream, dV, c->nbf);
+    XC_HIP(hipGetLastError());
+    if (c->n_batches > 0) {
+        hipLaunchKernelGGL(k_reduce_en, dim3(1), dim3(256), 0, c->stream,
+                           (const double*)c->epart.p, (const double*)c->npart.p,
+                           c->n_batches, dEN);
+    } else {
+        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, c->stream, dEN, 2LL, 0.0);
+    }
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
+}  // namespace xc

@@ -1,0 +1,191 @@
+// Internal declarations shared by the HIP sources of the XC library.
+// Device structures, the context, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "xc.h"
+
+namespace xc {
+
+// ---------------------------------------------------------------- errors --
+// Set the calling thread's error message and return code.
+int fail(int code, const std::string& msg);
+// Map a HIP status to XC_ERR_DEVICE with a message naming the call site.
+int hip_fail(hipError_t e, const char* what);
+
+#define XC_HIP(call)                                           \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return ::xc::hip_fail(e_, #call); \
+    } while (0)
+
+#define XC_TRY(call)                \
+    do {                            \
+        int r_ = (call);            \
+        if (r_ != XC_OK) return r_; \
+    } while (0)
+
+// ------------------------------------------------------ device structures --
+constexpr int kMaxL = 3;
+constexpr int kMaxPrim = 16;
+constexpr int kMaxBatch = 1024;     // largest batch_max accepted
+constexpr int kTile = 64;           // contraction tile edge (rows and columns)
+constexpr int kRowPad = 16;         // n_b is stored padded to a multiple of this
+constexpr int kColPad = 64;         // n_g is stored padded to a multiple of this
+
+// One basis shell as the kernels read it.
+struct ShellDev {
+    double x, y, z;     // centre
+    double rcut2;       // squared cutoff radius (eq. rcut); +inf: no truncation
+    int L;
+    int nprim;
+    int prim_off;       // first primitive in the packed exponent/coefficient arrays
+    int first_func;     // global index of the shell's first function
+};
+
+// A cuboid cell of points during batching, and a finished batch.
+struct Cell {
+    long long begin;    // first point (into the compacted point arrays)
+    int count;
+    int atom;           // parent atom
+    double lo[3];
+    double hi[3];
+};
+
+// One batch as the integration kernels of a wave read it.
+struct WaveBatch {
+    long long phi_off;  // offset (doubles) of slab 0 of this batch in the wave scratch
+    long long part_off; // offset (doubles) of its density partials
+    long long pt_off;   // first point
+    long long shell_off;// first entry in the shell list
+    long long func_off; // first entry in the function list
+    int nb;             // screened function count n_b
+    int nbp;            // n_b padded to kRowPad
+    int ng;             // point count n_g
+    int ngp;            // n_g padded to kColPad
+    int nmt;            // row tiles: ceil(n_b / kTile)
+    int nshell;
+    int batch;          // global batch index
+    int pad_;
+};
+
+struct Wave {
+    int first;          // first batch (global index)
+    int count;          // number of batches
+    int gemm_tiles;
+    int syr_tiles;
+    long long wb_off;   // offset into the WaveBatch array
+    long long pre_off;  // offset into the tile-prefix arrays (count + 1 entries)
+    size_t scratch_bytes;
+};
+
+// ------------------------------------------------------------- context ----
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+// HIP-event phase timer: pairs of events recorded around launches, folded
+// into milliseconds when the caller asks for the totals.
+struct PhaseTimer {
+    bool enabled = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[XC_NUM_PHASES];
+    std::vector<hipEvent_t> pool;
+    double ms[XC_NUM_PHASES] = {};
+    long long launches[XC_NUM_PHASES] = {};
+};
+
+}  // namespace xc
+
+struct xc_context {
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // inputs (host copies)
+    int natoms = 0;
+    std::vector<double> atoms4;       // x, y, z, mk_alpha per atom
+    int nshells = 0;
+    std::vector<int> shell_atom, shell_L, shell_nprim, prim_off, first_func;
+    std::vector<double> prim_alpha, prim_coef;
+    int nbf = 0;
+    int n_rad = 0, n_ang = 0;
+    std::vector<double> ang;          // n_ang x 4
+    double ssf_a = 0.64, screen_eta = 1e-10, rho_thresh = 1e-15;
+    int batch_max = 512;
+    std::vector<int> gatoms;          // parent atoms whose grids are built
+    size_t wave_budget = 0;
+
+    // device inputs
+    xc::DevBuf d_atoms, d_invR, d_nnhalf, d_shells, d_palpha, d_pcoef, d_ang, d_gatoms;
+
+    // grid and batches
+    bool built = false;
+    long long n_nominal = 0, n_points = 0;
+    xc::DevBuf raw_x, raw_y, raw_z, raw_w;                 // unpruned grid
+    xc::DevBuf px, py, pz, pw, pidx, tx, ty, tz, tw, tidx;  // compacted (batch order) + temp
+    xc::DevBuf blk_count, blk_off, atom_count;
+    xc::DevBuf cells_a, cells_b, child_count, child_begin, batches, counters;
+    std::vector<xc::Cell> h_batches;
+    long long n_batches = 0;
+    xc::DevBuf scr_nsh, scr_nfn, scr_shoff, scr_fnoff;
+    xc::DevBuf shell_list, shell_loff, func_list;
+    long long n_shell_entries = 0, n_func_entries = 0;
+    std::vector<int> h_nsh, h_nfn;
+    std::vector<long long> h_shoff, h_fnoff;
+
+    // wave plan
+    std::vector<xc::Wave> waves;
+    std::vector<xc::WaveBatch> h_wb;
+    xc::DevBuf d_wb, d_gemm_pre, d_syr_pre;
+    xc::DevBuf scratch;
+    size_t max_wave_bytes = 0;
+    xc::DevBuf epart, npart;
+
+    xc::PhaseTimer timer;
+
+    // statistics
+    int max_nb = 0, max_ng = 0;
+    double sum_nb_ng = 0, sum_nb2_ng = 0, flops_contract = 0;
+};
+
+namespace xc {
+
+// Brackets the launches issued during its lifetime with timer events when
+// the context's timer is on.
+class PhaseScope {
+  public:
+    PhaseScope(xc_context* c, int phase);
+    ~PhaseScope();
+
+  private:
+    xc_context* c_;
+    int phase_;
+    hipEvent_t e0_ = nullptr;
+};
+
+// device memory helpers (context stream ordered where relevant)
+int dev_reserve(DevBuf& b, size_t bytes);
+void dev_release(DevBuf& b);
+int upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s);
+
+// grid.hip
+int launch_shell_setup(xc_context* c);
+int launch_grid_points(xc_context* c);
+int launch_ssf(xc_context* c);
+int launch_compact(xc_context* c, std::vector<long long>& atom_kept);
+
+// batching.hip
+int run_batching(xc_context* c, const std::vector<long long>& atom_kept);
+int run_screening(xc_context* c);
+
+// integrate.hip
+int run_integrate(xc_context* c, int functional, const double* dP, double* dV,
+                  double* dEN);
+
+}  // namespace xc

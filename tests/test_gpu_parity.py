@@ -1,0 +1,164 @@
+"""HIP path against the oracle, through the C ABI (Sec. 2.1-2.3).
+
+Tolerances: |dE_xc| <= 1e-10 Eh and max|dV_xc| <= 1e-10 for FP64; grid
+points and weights to 1e-13 relative; batching and screening lists exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import gpu_integrate, oracle_integrate, say
+from workloads import cfg_water, cfg_water_cluster, grid_spec_dict, make_basis
+from workloads.molecules import Molecule
+from workloads.configs import Workload
+from workloads.basis import overlap_matrix
+from workloads.density import random_density
+
+pytestmark = pytest.mark.gpu
+
+TOL_E = 1e-10
+TOL_V = 1e-10
+
+
+def _check(w, functional, **kw):
+    say(f"case {w.name} {functional} " + str({k: (np.nonzero(v)[0].tolist() if k == 'atom_mask' else v) for k, v in kw.items()}))
+    E, N, V, st = gpu_integrate(w, functional, **kw)
+    okw = {k: v for k, v in kw.items() if k in ("atom_mask", "screen_eta", "n_rad")}
+    Eo, No, Vo = oracle_integrate(w, functional, **okw)
+    say(f"  E gpu {E!r} oracle {Eo!r} dE {E - Eo:.3e} dN {N - No:.3e} "
+        f"max dV {np.abs(V - Vo).max():.3e} batches {st['n_batches']}")
+    assert abs(E - Eo) <= TOL_E
+    assert abs(N - No) <= TOL_E
+    assert np.abs(V - Vo).max() <= TOL_V
+    assert np.array_equal(V, V.T)
+    return E, N, V, st
+
+
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_water_parity(functional):
+    _check(cfg_water(), functional)
+
+
+def test_water_no_truncation_parity():
+    _check(cfg_water(n_rad=40, n_ang=146), "pbe", screen_eta=0.0)
+
+
+def test_single_atom_parity():
+    Z = np.array([1])
+    X = np.array([[0.3, -0.2, 0.1]])
+    b = make_basis(Z)
+    S = overlap_matrix(b, X)
+    P = random_density(S, 1, seed=3) + 0.01 * np.eye(b.nbf)
+    w = Workload("h_atom", Molecule(Z.astype(np.int32), X), b, P, 1, 50, 194, "pbe")
+    for f in ("lda", "pbe"):
+        _check(w, f)
+
+
+def test_empty_mask_gives_zero():
+    w = cfg_water()
+    E, N, V, st = gpu_integrate(w, "pbe", atom_mask=np.zeros(3, np.uint8))
+    assert E == 0.0 and N == 0.0 and not V.any() and st["n_points"] == 0
+
+
+def test_mask_parity_and_additivity():
+    w = cfg_water()
+    m = np.array([1, 0, 1], np.uint8)
+    Ea, Na, Va, _ = _check(w, "pbe", atom_mask=m)
+    Eb, Nb, Vb, _ = gpu_integrate(w, "pbe", atom_mask=1 - m)
+    E, N, V, _ = gpu_integrate(w, "pbe")
+    assert abs(Ea + Eb - E) <= 1e-12 * abs(E)
+    assert np.abs(Va + Vb - V).max() <= 1e-12 * np.abs(V).max()
+
+
+@pytest.mark.parametrize("batch_max,wave_bytes", [(64, 0), (1024, 0), (512, 1 << 20)])
+def test_batching_and_wave_invariance(batch_max, wave_bytes):
+    w = cfg_water()
+    E0, N0, V0, st0 = gpu_integrate(w, "pbe")
+    E, N, V, st = gpu_integrate(w, "pbe", batch_max=batch_max, wave_bytes=wave_bytes)
+    say(f"  batch_max {batch_max} waves {st['n_waves']} batches {st['n_batches']}")
+    assert st["max_ng"] <= batch_max
+    assert abs(E - E0) <= 1e-12 * abs(E0)
+    assert np.abs(V - V0).max() <= 1e-12 * np.abs(V0).max()
+
+
+def test_repeat_runs_deterministic():
+    w = cfg_water()
+    E1, N1, V1, _ = gpu_integrate(w, "pbe")
+    E2, N2, V2, _ = gpu_integrate(w, "pbe")
+    assert E1 == E2 and N1 == N2
+    assert np.abs(V1 - V2).max() <= 1e-14 * np.abs(V1).max()
+
+
+def _grid_ctx(w, **over):
+    from paper_2007_03143_amd import XcContext
+    ctx = XcContext(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w, **over))
+    ctx.build_grid()
+    return ctx
+
+
+def test_grid_points_and_weights_match_oracle():
+    w = cfg_water()
+    say("case grid export water")
+    ctx = _grid_ctx(w)
+    try:
+        xyzw, idx = ctx.export_grid()
+    finally:
+        ctx.close()
+    pts, wq, par = oracle.molecular_grid(w.coords, w.mk_alpha, w.n_rad, w.ang)
+    wo = oracle.ssf_weights(pts, wq, par, w.coords)
+    assert len(np.unique(idx)) == len(idx)
+    assert np.abs(xyzw[:, :3] - pts[idx]).max() <= 1e-13 * np.abs(pts).max()
+    full = np.zeros_like(wo)
+    full[idx] = xyzw[:, 3]
+    assert np.all(np.abs(full - wo) <= 1e-13 * wq)
+    # every dropped point had zero weight up to the partition's rounding
+    dropped = np.setdiff1d(np.arange(len(wo)), idx)
+    assert np.all(wo[dropped] <= 1e-13 * wq[dropped])
+
+
+@pytest.mark.parametrize("name", ["water", "cluster8"])
+def test_batches_and_screening_lists(name):
+    w = cfg_water() if name == "water" else cfg_water_cluster(8, functional="pbe",
+                                                               n_rad=40, n_ang=110)
+    say(f"case batches {name}")
+    ctx = _grid_ctx(w)
+    try:
+        xyzw, idx = ctx.export_grid()
+        pp, bb, sp, sh = ctx.export_batches()
+        st = ctx.stats()
+    finally:
+        ctx.close()
+    n = xyzw.shape[0]
+    assert pp[0] == 0 and pp[-1] == n and np.all(np.diff(pp) >= 1)
+    assert np.all(np.diff(pp) <= w.batch_max)
+    rng = np.random.default_rng(0)
+    nb = len(pp) - 1
+    check = np.arange(nb) if nb <= 400 else rng.choice(nb, 400, replace=False)
+    rc2 = np.array([oracle.shell_rcut(w.basis.shell(s)[2], w.screen_eta) ** 2
+                    for s in range(w.basis.nshells)])
+    cen = w.coords[w.basis.shell_atom]
+    for j in check:
+        p = xyzw[pp[j]:pp[j + 1], :3]
+        assert np.array_equal(bb[j, :3], p.min(0)) and np.array_equal(bb[j, 3:], p.max(0))
+        ref = oracle.screen_batch(p, w.coords, w.basis, w.screen_eta)
+        got = sh[sp[j]:sp[j + 1]]
+        assert list(got) == ref, j
+        # conservative: every shell that reaches a point of the batch is listed
+        d2 = ((p[:, None, :] - cen[None]) ** 2).sum(-1)
+        reach = np.nonzero((d2 <= rc2[None]).any(0))[0]
+        assert set(reach) <= set(got)
+    # batches never straddle parent atoms
+    parent = idx // (w.n_rad * w.n_ang)
+    for j in check:
+        assert len(np.unique(parent[pp[j]:pp[j + 1]])) == 1
+
+
+@pytest.mark.parametrize("atom", [0, 100])
+def test_cluster_sampled_atoms_parity(atom):
+    """The 64-water cluster at full size (192 atoms, 1600 functions, 100 x 590
+    grid); the oracle checks the integrals over one parent atom's grid
+    (an O and an H)."""
+    w = cfg_water_cluster()
+    mask = np.zeros(w.natoms, np.uint8)
+    mask[atom] = 1
+    _check(w, "pbe", atom_mask=mask)

@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--wave-gb", type=float, default=0.0)
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-merge", type=int, default=1)
+    ap.add_argument("--mixed", default="fp32")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -93,7 +95,8 @@ def main():
 
     log(f"building workload {args.workload}")
     w, functional = make_workload(args.workload)
-    ctx = XcContext(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w),
+    ctx = XcContext(w.coords, w.mk_alpha, w.basis,
+                    grid_spec_dict(w, batch_merge=args.batch_merge),
                     wave_bytes=int(args.wave_gb * (1 << 30)))
     P = torch.from_numpy(w.P).cuda()
     torch.cuda.synchronize()
@@ -133,6 +136,25 @@ def main():
     V = ctx.V.cpu().numpy()
     log(f"warm {ms_warm:.1f} ms/step; E_xc {EN[0]!r} N_e {EN[1]!r}")
 
+    # mixed precision: FP32 collocation and contractions, FP64 functional/sums
+    mixed = {}
+    for prec in args.mixed.split(",") if args.mixed else []:
+        ctx.integrate(P, functional, prec)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for i in range(args.steps):
+            ctx.integrate(P, functional, prec)
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t4) * 1e3 / args.steps
+        ENm = ctx.EN.cpu().numpy()
+        Vm = ctx.V.cpu().numpy()
+        mixed[prec] = {"warm_value": n_nom / (ms_m * 1e-3), "warm_ms_per_step": ms_m,
+                       "speedup_vs_fp64_warm": ms_warm / ms_m,
+                       "dE_xc_vs_fp64": float(ENm[0] - EN[0]),
+                       "dN_e_vs_fp64": float(ENm[1] - EN[1]),
+                       "max_dV_vs_fp64": float(np.abs(Vm - V).max())}
+        log(f"{prec}: {ms_m:.1f} ms/step, dE {ENm[0] - EN[0]:.3e}")
+
     # roofline of the dominant kernel (HIP events inside the timed region)
     flops = {"density": 2.0 * st["sum_nb2_ng"],
              "potential": 2.0 * (st["sum_nb2_ng"] + st["sum_nb_ng"])}
@@ -162,10 +184,12 @@ def main():
                    "mean_nb_point_weighted": st["sum_nb_ng"] / max(st["n_points"], 1),
                    "max_nb": st["max_nb"], "n_waves": st["n_waves"],
                    "precision": "fp64", "parallelism": "single GPU",
+                   "batch_merge": args.batch_merge,
                    "step": "grid build + weights + batching + screening + integration"},
         "warm": {"value": n_nom / (ms_warm * 1e-3), "ms_per_step": ms_warm,
                  "step": "integration with the grid reused"},
         "phase_ms_per_step": phase_ms,
+        "mixed": mixed,
         "contractions_tflops": both,
         "roofline": roof,
         "E_xc": float(EN[0]), "N_e": float(EN[1]),

@@ -55,7 +55,9 @@ extern "C" {
 
 /* arithmetic of the collocation and the two batched contractions */
 #define XC_FP64          0   /* everything FP64 */
-#define XC_MIXED_FP32    1   /* reserved: FP32 contractions, FP64 functional and sums */
+#define XC_MIXED_FP32    1   /* FP32 collocation and contractions (FP32 MFMA, FP32
+                                accumulate); FP64 functional, Z formation, E_xc/N_e
+                                sums and V accumulation */
 #define XC_MIXED_BF16X3  2   /* reserved: split-BF16 contractions with FP32 accumulate */
 
 /*
@@ -99,6 +101,10 @@ typedef struct xc_basis {
  *  rho_thresh  points with rho below it add nothing to E_xc and V_xc
  *  atom_mask   NULL, or natoms flags: only the grids of flagged parent atoms
  *              are integrated (the partition still uses every atom)
+ *  batch_merge 0: every non-empty cuboid of the recursive split is a batch;
+ *              1: consecutive small sibling cuboids are joined while the
+ *              joined count stays <= batch_max (fewer, fuller batches; the
+ *              result is the same either way)
  */
 typedef struct xc_grid_spec {
     int n_rad;
@@ -109,6 +115,7 @@ typedef struct xc_grid_spec {
     int batch_max;
     double rho_thresh;
     const unsigned char* atom_mask;
+    int batch_merge;
 } xc_grid_spec;
 
 /*

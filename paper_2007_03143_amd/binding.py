@@ -47,7 +47,8 @@ class XcBasis(Structure):
 class XcGridSpec(Structure):
     _fields_ = [("n_rad", c_int), ("n_ang", c_int), ("ang_xyzw", POINTER(c_double)),
                 ("ssf_a", c_double), ("screen_eta", c_double), ("batch_max", c_int),
-                ("rho_thresh", c_double), ("atom_mask", POINTER(c_ubyte))]
+                ("rho_thresh", c_double), ("atom_mask", POINTER(c_ubyte)),
+                ("batch_merge", c_int)]
 
 
 class XcDeviceOpts(Structure):
@@ -164,7 +165,8 @@ class _Inputs:
             int(grid["n_rad"]), int(grid["n_ang"]), _dptr(self.ang),
             float(grid.get("ssf_a", 0.64)), float(grid.get("screen_eta", 1e-10)),
             int(grid.get("batch_max", 512)), float(grid.get("rho_thresh", 1e-15)),
-            None if self.mask is None else self.mask.ctypes.data_as(POINTER(c_ubyte)))
+            None if self.mask is None else self.mask.ctypes.data_as(POINTER(c_ubyte)),
+            int(grid.get("batch_merge", 1)))
         self.nbf = int(sum((L + 1) * (L + 2) // 2 for L in self.sl))
 
 

@@ -167,7 +167,8 @@ static int validate_inputs(const xc_molecule* mol, const xc_basis* basis,
 static int check_func_prec(int functional, int precision) {
     if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE)
         return fail(XC_ERR_UNSUPPORTED, "unknown functional");
-    if (precision != XC_FP64) return fail(XC_ERR_UNSUPPORTED, "only XC_FP64 is available");
+    if (precision != XC_FP64 && precision != XC_MIXED_FP32)
+        return fail(XC_ERR_UNSUPPORTED, "precision not available");
     return XC_OK;
 }
 
@@ -368,6 +369,7 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
     c->screen_eta = g->screen_eta;
     c->rho_thresh = g->rho_thresh;
     c->batch_max = g->batch_max;
+    c->batch_merge = g->batch_merge ? 1 : 0;
     for (int a = 0; a < c->natoms; ++a)
         if (!g->atom_mask || g->atom_mask[a]) c->gatoms.push_back(a);
     hipError_t e = hipGetDevice(&c->device);
@@ -411,7 +413,7 @@ int xc_context_integrate(xc_context* c, int functional, int precision, const dou
     if (!dP || !dV || !dEN) return fail(XC_ERR_INVALID_ARG, "null device buffer");
     XC_TRY(check_func_prec(functional, precision));
     if (!c->built) XC_TRY(build_grid(c));
-    return run_integrate(c, functional, dP, dV, dEN);
+    return run_integrate(c, functional, precision, dP, dV, dEN);
 }
 
 int xc_context_stats(xc_context* c, xc_stats* s) {
@@ -541,8 +543,8 @@ int xc_integrate(const xc_molecule* mol, const xc_basis* basis, const xc_grid_sp
     if (rc == XC_OK) rc = upload(dP, P, mb, c->stream);
     if (rc == XC_OK) rc = dev_reserve(dV, mb);
     if (rc == XC_OK) rc = dev_reserve(dEN, 16);
-    if (rc == XC_OK) rc = run_integrate(c, functional, (const double*)dP.p, (double*)dV.p,
-                                        (double*)dEN.p);
+    if (rc == XC_OK) rc = run_integrate(c, functional, precision, (const double*)dP.p,
+                                        (double*)dV.p, (double*)dEN.p);
     double en[2] = {0.0, 0.0};
     std::vector<double> hv;
     if (rc == XC_OK) {

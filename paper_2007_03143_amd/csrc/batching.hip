@@ -149,35 +149,76 @@ __global__ __launch_bounds__(256) void k_split(
     }
 }
 
-// Single workgroup: walk the children in order and append the non-empty ones
-// either to the finished batches (count <= batch_max) or to the next level.
-// counters[0] = batches written, counters[1] = next-level cells written.
+// Single workgroup: walk every parent's children in order and append the
+// non-empty ones either to the finished batches (count <= batch_max) or to
+// the next level. With merge on, runs of consecutive small children of one
+// parent (their points are contiguous) are joined while the joined count
+// stays <= batch_max. counters[0] = batches written, counters[1] = next-level
+// cells written.
+__device__ inline int classify_parent(const int* cnt, const long long* beg,
+                                      int batch_max, int merge, int atom,
+                                      Cell* ob, Cell* on, bool write) {
+    int nb = 0, nn = 0;
+    long long gb = 0;
+    int gc = 0;
+    auto emit = [&](Cell* dst, int idx, long long b, int n) {
+        if (!write) return;
+        Cell o;
+        o.begin = b;
+        o.count = n;
+        o.atom = atom;
+        for (int q = 0; q < 3; ++q) {
+            o.lo[q] = 0.0;
+            o.hi[q] = 0.0;
+        }
+        dst[idx] = o;
+    };
+    for (int k = 0; k < kMaxChild; ++k) {
+        const int n = cnt[k];
+        if (n == 0) continue;
+        if (n > batch_max) {
+            if (gc > 0) emit(ob, nb++, gb, gc);
+            gc = 0;
+            emit(on, nn++, beg[k], n);
+        } else if (!merge) {
+            emit(ob, nb++, beg[k], n);
+        } else {
+            if (gc > 0 && gc + n > batch_max) {
+                emit(ob, nb++, gb, gc);
+                gc = 0;
+            }
+            if (gc == 0) gb = beg[k];
+            gc += n;
+        }
+    }
+    if (gc > 0) emit(ob, nb++, gb, gc);
+    return (nb << 16) | nn;
+}
+
 __global__ __launch_bounds__(1024) void k_classify(
     const int* child_count, const long long* child_begin, const Cell* parents,
-    int nchild_total, int batch_max, Cell* out_batches, Cell* out_next,
+    int nparents, int batch_max, int merge, Cell* out_batches, Cell* out_next,
     int* counters) {
     __shared__ int smem[17];
     int nb = 0, nn = 0;
-    for (int c0 = 0; c0 < nchild_total; c0 += blockDim.x) {
-        const int i = c0 + threadIdx.x;
-        const int cnt = (i < nchild_total) ? child_count[i] : 0;
-        const int isb = (cnt > 0 && cnt <= batch_max);
-        const int isn = (cnt > batch_max);
-        int tb, tn;
-        const int pb = block_exclusive_scan(isb, smem, tb);
-        const int pn = block_exclusive_scan(isn, smem, tn);
-        if (isb || isn) {
-            Cell o;
-            o.begin = child_begin[i];
-            o.count = cnt;
-            o.atom = parents[i / kMaxChild].atom;
-            for (int q = 0; q < 3; ++q) {
-                o.lo[q] = 0.0;
-                o.hi[q] = 0.0;
-            }
-            if (isb) out_batches[nb + pb] = o;
-            else out_next[nn + pn] = o;
+    for (int p0 = 0; p0 < nparents; p0 += blockDim.x) {
+        const int p = p0 + threadIdx.x;
+        int cb = 0, cn = 0;
+        const int* cnt = child_count + (size_t)p * kMaxChild;
+        const long long* beg = child_begin + (size_t)p * kMaxChild;
+        const int atom = (p < nparents) ? parents[p].atom : 0;
+        if (p < nparents) {
+            const int r = classify_parent(cnt, beg, batch_max, merge, atom, nullptr,
+                                          nullptr, false);
+            cb = r >> 16;
+            cn = r & 0xffff;
         }
+        int tb, tn;
+        const int pb = block_exclusive_scan(cb, smem, tb);
+        const int pn = block_exclusive_scan(cn, smem, tn);
+        if (p < nparents)
+            classify_parent(cnt, beg, batch_max, merge, atom, out_batches + nb + pb,
+                            out_next + nn + pn, true);
         nb += tb;
         nn += tn;
     }
@@ -234,7 +275,7 @@ int run_batching(xc_context* c, const std::vector<long long>& atom_kept) {
         hipLaunchKernelGGL(k_classify, dim3(1), dim3(1024), 0, c->stream,
                            (const int*)c->child_count.p,
                            (const long long*)c->child_begin.p,
-                           (const Cell*)c->cells_a.p, (int)nch, c->batch_max,
+                           (const Cell*)c->cells_a.p, ncur, c->batch_max, c->batch_merge,
                            (Cell*)c->batches.p, (Cell*)c->cells_b.p, (int*)c->counters.p);
         XC_HIP(hipGetLastError());
         int cnt[2];

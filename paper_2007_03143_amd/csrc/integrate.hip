@@ -19,24 +19,47 @@
 #include "functional.hpp"
 #include "xc_internal.hpp"
 
+// Accumulator row of register r in lane l for the FP32 16x16x4 MFMA.
+#ifndef XC_F32_ACC_ROW
+#define XC_F32_ACC_ROW(r, lane) (4 * (r) + ((lane) >> 4))
+#endif
+
 namespace xc {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ inline v4d mfma64(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// 16x16x4 MFMA of the storage type: FP64 (v_mfma_f64_16x16x4f64) or FP32
+// (v_mfma_f32_16x16x4f32). Operand lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator register r of lane l holds C[row][l % 16]
+// with row = acc_row(r, l).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    using acc = v4d;
+    __device__ static inline acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static inline acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int acc_row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+    using acc = v4f;
+    __device__ static inline acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static inline acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int acc_row(int r, int lane) { return XC_F32_ACC_ROW(r, lane); }
+};
 
 // ------------------------------------------------------------ collocation --
 // Values (and gradients) of the (L+1)(L+2)/2 Cartesian functions of one
 // shell at one point, written down the rows starting at out (row stride ngp;
 // gradients at +slab, +2 slab, +3 slab).
-template <int L, bool GGA>
-__device__ inline void colloc_shell(double dx, double dy, double dz, double rad,
-                                    double drad, bool live, double* out, int ngp,
-                                    size_t slab) {
-    double xp[L + 1], yp[L + 1], zp[L + 1];
-    xp[0] = yp[0] = zp[0] = 1.0;
+template <int L, bool GGA, typename T>
+__device__ inline void colloc_shell(T dx, T dy, T dz, T rad, T drad, bool live, T* out,
+                                    int ngp, size_t slab) {
+    T xp[L + 1], yp[L + 1], zp[L + 1];
+    xp[0] = yp[0] = zp[0] = T(1);
 #pragma unroll
     for (int k = 1; k <= L; ++k) {
         xp[k] = xp[k - 1] * dx;
@@ -49,22 +72,22 @@ __device__ inline void colloc_shell(double dx, double dy, double dz, double rad,
 #pragma unroll
         for (int m = L - l; m >= 0; --m) {
             const int n = L - l - m;
-            double* o = out + (size_t)c * ngp;
+            T* o = out + (size_t)c * ngp;
             if (!live) {
-                o[0] = 0.0;
+                o[0] = T(0);
                 if (GGA) {
-                    o[slab] = 0.0;
-                    o[2 * slab] = 0.0;
-                    o[3 * slab] = 0.0;
+                    o[slab] = T(0);
+                    o[2 * slab] = T(0);
+                    o[3 * slab] = T(0);
                 }
             } else {
-                const double ang = xp[l] * yp[m] * zp[n];
+                const T ang = xp[l] * yp[m] * zp[n];
                 o[0] = ang * rad;
                 if (GGA) {
-                    const double ad = ang * drad;
-                    const double gx = (l ? l * xp[l - 1] * yp[m] * zp[n] : 0.0);
-                    const double gy = (m ? m * xp[l] * yp[m - 1] * zp[n] : 0.0);
-                    const double gz = (n ? n * xp[l] * yp[m] * zp[n - 1] : 0.0);
+                    const T ad = ang * drad;
+                    const T gx = (l ? T(l) * xp[l - 1] * yp[m] * zp[n] : T(0));
+                    const T gy = (m ? T(m) * xp[l] * yp[m - 1] * zp[n] : T(0));
+                    const T gz = (n ? T(n) * xp[l] * yp[m] * zp[n - 1] : T(0));
                     o[slab] = gx * rad + ad * dx;
                     o[2 * slab] = gy * rad + ad * dy;
                     o[3 * slab] = gz * rad + ad * dz;
@@ -78,13 +101,13 @@ __device__ inline void colloc_shell(double dx, double dy, double dz, double rad,
 // One workgroup per batch; wave w evaluates shells w, w+4, ... of the
 // batch's screened list, one lane per point, so a wave never diverges on
 // the contraction length. Points of the batch are staged in LDS.
-template <bool GGA>
+template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_colloc(
     const WaveBatch* __restrict__ wb, const ShellDev* __restrict__ shells,
     const double* __restrict__ palpha, const double* __restrict__ pcoef,
     const int* __restrict__ shell_list, const int* __restrict__ shell_loff,
     const double* __restrict__ X, const double* __restrict__ Y,
-    const double* __restrict__ Z, double* __restrict__ scratch) {
+    const double* __restrict__ Z, char* __restrict__ scratch) {
     const WaveBatch B = wb[blockIdx.x];
     __shared__ double sx[kMaxBatch], sy[kMaxBatch], sz[kMaxBatch];
     for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
@@ -94,17 +117,17 @@ __global__ __launch_bounds__(256) void k_colloc(
         sz[i] = v ? Z[B.pt_off + i] : 0.0;
     }
     __syncthreads();
-    double* Phi = scratch + B.phi_off;
+    T* Phi = (T*)(scratch + 8 * B.phi_off);
     const size_t slab = (size_t)B.nbp * B.ngp;
     // zero the padding rows n_b .. n_bp - 1
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) {
         const size_t off = (size_t)B.nb * B.ngp + k;
-        Phi[off] = 0.0;
+        Phi[off] = T(0);
         if (GGA) {
-            Phi[slab + off] = 0.0;
-            Phi[2 * slab + off] = 0.0;
-            Phi[3 * slab + off] = 0.0;
+            Phi[slab + off] = T(0);
+            Phi[2 * slab + off] = T(0);
+            Phi[3 * slab + off] = T(0);
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -122,21 +145,23 @@ __global__ __launch_bounds__(256) void k_colloc(
                 r2 = dx * dx + dy * dy + dz * dz;
             }
             const bool live = (i < B.ng) && (r2 <= sh.rcut2);
-            double rad = 0.0, drad = 0.0;
+            T rad = T(0), drad = T(0);
             if (live) {
+                const T tr2 = T(r2);
                 for (int p = 0; p < sh.nprim; ++p) {
-                    const double a = palpha[sh.prim_off + p];
-                    const double de = pcoef[sh.prim_off + p] * exp(-a * r2);
+                    const T a = T(palpha[sh.prim_off + p]);
+                    const T de = T(pcoef[sh.prim_off + p]) * exp(-a * tr2);
                     rad += de;
-                    drad -= 2.0 * a * de;
+                    drad -= T(2) * a * de;
                 }
             }
-            double* out = Phi + (size_t)loff * B.ngp + i;
+            T* out = Phi + (size_t)loff * B.ngp + i;
+            const T tx = T(dx), ty = T(dy), tz = T(dz);
             switch (sh.L) {
-                case 0: colloc_shell<0, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
-                case 1: colloc_shell<1, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
-                case 2: colloc_shell<2, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
-                default: colloc_shell<3, GGA>(dx, dy, dz, rad, drad, live, out, B.ngp, slab); break;
+                case 0: colloc_shell<0, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
+                case 1: colloc_shell<1, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
+                case 2: colloc_shell<2, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
+                default: colloc_shell<3, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
             }
         }
     }
@@ -148,11 +173,12 @@ __global__ __launch_bounds__(256) void k_colloc(
 // the full P through the batch's function list. The epilogue reduces
 // Phi*X (and grad Phi * X) over the tile's rows into per-row-tile partials
 // part[mt][q][point], q = rho, dx, dy, dz.
-template <bool GGA>
+template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_gemm_rho(
     const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
     int ntiles, const double* __restrict__ P, int nbf,
-    const int* __restrict__ func_list, double* __restrict__ scratch) {
+    const int* __restrict__ func_list, char* __restrict__ scratch) {
+    using M = Mfma<T>;
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int bi = find_segment(prefix, nwb, t);
     const WaveBatch B = wb[bi];
@@ -161,11 +187,11 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
     const size_t slab = (size_t)B.nbp * B.ngp;
-    const double* Phi = scratch + B.phi_off;
+    const T* Phi = (const T*)(scratch + 8 * B.phi_off);
     const int* fl = func_list + B.func_off;
 
-    __shared__ double As[2][kTile][17];
-    __shared__ double Bs[2][16][kTile + 1];
+    __shared__ T As[2][kTile][17];
+    __shared__ T Bs[2][16][kTile + 1];
     __shared__ int frow[kTile];
     __shared__ double red[4][kTile];
 
@@ -179,15 +205,20 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int fr = frow[ar];
     const double* Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
 
-    double ra[4], rb[4];
-    auto gload = [&](int ks) {
-        const int k0 = ks * 16;
+    // The P^j columns of a K step are gathered through the function list;
+    // those indices are fetched one step ahead of the P loads that use them
+    // so the two dependent global loads never sit back to back.
+    T ra[4], rb[4];
+    int fc[4];
+    auto fload = [&](int ks) {
+        const int k0 = ks * 16 + ac;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int kk = k0 + ac + q;
-            ra[q] = (fr >= 0 && kk < B.nb) ? Prow[fl[kk]] : 0.0;
-        }
-        const double* src = Phi + (size_t)(k0 + br) * B.ngp + n0 + bc;
+        for (int q = 0; q < 4; ++q) fc[q] = (k0 + q < B.nb) ? fl[k0 + q] : -1;
+    };
+    auto gload = [&](int ks) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = (fr >= 0 && fc[q] >= 0) ? T(Prow[fc[q]]) : T(0);
+        const T* src = Phi + (size_t)(ks * 16 + br) * B.ngp + n0 + bc;
 #pragma unroll
         for (int q = 0; q < 4; ++q) rb[q] = src[q];
     };
@@ -199,22 +230,27 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         }
     };
 
-    v4d acc[2][2];
+    typename M::acc acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
 
     const int nk = B.nbp / 16;
+    fload(0);
     gload(0);
     sstore(0);
+    if (nk > 1) fload(1);
     __syncthreads();
     for (int ks = 0; ks < nk; ++ks) {
         const int cur = ks & 1;
-        if (ks + 1 < nk) gload(ks + 1);
+        if (ks + 1 < nk) {
+            gload(ks + 1);
+            if (ks + 2 < nk) fload(ks + 2);
+        }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            double a[2], b[2];
+            T a[2], b[2];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
                 a[mb] = As[cur][wm * 32 + mb * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
@@ -224,7 +260,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma64(a[mb], b[nb], acc[mb][nb]);
+                for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = M::mma(a[mb], b[nb], acc[mb][nb]);
         }
         if (ks + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
@@ -238,18 +274,18 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = m0 + wm * 32 + mb * 16 + 4 * r + (lane >> 4);
+            const int row = m0 + wm * 32 + mb * 16 + M::acc_row(r, lane);
             if (row < B.nb) {
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb) {
                     const int col = n0 + wn * 32 + nb * 16 + (lane & 15);
-                    const double x = acc[mb][nb][r];
+                    const T x = acc[mb][nb][r];
                     const size_t off = (size_t)row * B.ngp + col;
-                    q[0][nb] += Phi[off] * x;
+                    q[0][nb] += double(Phi[off] * x);
                     if (GGA) {
-                        q[1 % NQ][nb] += Phi[slab + off] * x;
-                        q[2 % NQ][nb] += Phi[2 * slab + off] * x;
-                        q[3 % NQ][nb] += Phi[3 * slab + off] * x;
+                        q[1 % NQ][nb] += double(Phi[slab + off] * x);
+                        q[2 % NQ][nb] += double(Phi[2 * slab + off] * x);
+                        q[3 % NQ][nb] += double(Phi[3 * slab + off] * x);
                     }
                 }
             }
@@ -272,7 +308,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     }
     __syncthreads();
     if (wm == 0 && lane < 16) {
-        double* part = scratch + B.part_off;
+        double* part = (double*)(scratch + 8 * B.part_off);
 #pragma unroll
         for (int qq = 0; qq < NQ; ++qq)
 #pragma unroll
@@ -284,15 +320,15 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 }
 
 // ------------------------------------------------- functional + Z matrix --
-template <bool GGA>
+template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_func_z(
     const WaveBatch* __restrict__ wb, const double* __restrict__ W, double rho_thresh,
-    double* __restrict__ scratch, double* __restrict__ epart,
+    char* __restrict__ scratch, double* __restrict__ epart,
     double* __restrict__ npart) {
     const WaveBatch B = wb[blockIdx.x];
     __shared__ double sa[kMaxBatch], sbx[kMaxBatch], sby[kMaxBatch], sbz[kMaxBatch];
     __shared__ double red[256];
-    const double* part = scratch + B.part_off;
+    const double* part = (const double*)(scratch + 8 * B.part_off);
     double eacc = 0.0, nacc = 0.0;
     for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
         double a = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
@@ -344,18 +380,21 @@ __global__ __launch_bounds__(256) void k_func_z(
         epart[B.batch] = es;
         npart[B.batch] = ns;
     }
-    // Z overwrites slab 1 (the x-gradient for the GGA, which is read first)
-    double* Phi = scratch + B.phi_off;
+    // Z overwrites slab 1 (the x-gradient for the GGA, which is read first);
+    // formed in FP64 and stored in the storage type
+    T* Phi = (T*)(scratch + 8 * B.phi_off);
     const size_t slab = (size_t)B.nbp * B.ngp;
-    double* Zm = Phi + slab;
+    T* Zm = Phi + slab;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int row = wave; row < B.nbp; row += 4) {
         const size_t ro = (size_t)row * B.ngp;
         for (int i = lane; i < B.ngp; i += 64) {
             const size_t off = ro + i;
-            double z = sa[i] * Phi[off];
-            if (GGA) z += sbx[i] * Zm[off] + sby[i] * Phi[2 * slab + off] + sbz[i] * Phi[3 * slab + off];
-            Zm[off] = z;
+            double z = sa[i] * double(Phi[off]);
+            if (GGA)
+                z += sbx[i] * double(Zm[off]) + sby[i] * double(Phi[2 * slab + off]) +
+                     sbz[i] * double(Phi[3 * slab + off]);
+            Zm[off] = T(z);
         }
     }
 }
@@ -364,10 +403,12 @@ __global__ __launch_bounds__(256) void k_func_z(
 // Lower-triangle tile (I >= J) of V^j = Z Phi^T + Phi Z^T, 64 x 64, over all
 // points of the batch, added into V[f(row)][f(col)] (f ascending, so the
 // global entry is in the lower triangle too).
+template <typename T>
 __global__ __launch_bounds__(256) void k_syr2k(
     const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
-    int ntiles, const int* __restrict__ func_list, const double* __restrict__ scratch,
+    int ntiles, const int* __restrict__ func_list, const char* __restrict__ scratch,
     double* __restrict__ V, int nbf) {
+    using M = Mfma<T>;
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int bi = find_segment(prefix, nwb, t);
     const WaveBatch B = wb[bi];
@@ -377,50 +418,53 @@ __global__ __launch_bounds__(256) void k_syr2k(
     while (I * (I + 1) / 2 > lt) --I;
     const int J = lt - I * (I + 1) / 2;
     const size_t slab = (size_t)B.nbp * B.ngp;
-    const double* Phi = scratch + B.phi_off;
-    const double* Zm = Phi + slab;
+    const T* Phi = (const T*)(scratch + 8 * B.phi_off);
+    const T* Zm = Phi + slab;
     const int* fl = func_list + B.func_off;
 
-    __shared__ double sZI[2][kTile][17], sPI[2][kTile][17];
-    __shared__ double sPJ[2][kTile][17], sZJ[2][kTile][17];
+    // K steps of 8 keep the four double-buffered operand tiles at 37 KB of
+    // LDS, so four workgroups fit on a CU.
+    constexpr int KS = 8;
+    __shared__ T sZI[2][kTile][KS + 1], sPI[2][kTile][KS + 1];
+    __shared__ T sPJ[2][kTile][KS + 1], sZJ[2][kTile][KS + 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int lr = tid >> 2, lc = (tid & 3) * 4;
+    const int lr = tid >> 2, lc = (tid & 3) * 2;
     const int rI = I * kTile + lr, rJ = J * kTile + lr;
     const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
-    const double* zI = Zm + (size_t)(vI ? rI : 0) * B.ngp;
-    const double* pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
-    const double* zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
-    const double* pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
+    const T* zI = Zm + (size_t)(vI ? rI : 0) * B.ngp;
+    const T* pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
+    const T* zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
+    const T* pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
 
-    double g[4][4];
+    T g[4][2];
     auto gload = [&](int ks) {
-        const int k0 = ks * 16 + lc;
+        const int k0 = ks * KS + lc;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            g[0][q] = vI ? zI[k0 + q] : 0.0;
-            g[1][q] = vI ? pI[k0 + q] : 0.0;
-            g[2][q] = vJ ? pJ[k0 + q] : 0.0;
-            g[3][q] = vJ ? zJ[k0 + q] : 0.0;
+        for (int q = 0; q < 2; ++q) {
+            g[0][q] = vI ? zI[k0 + q] : T(0);
+            g[1][q] = vI ? pI[k0 + q] : T(0);
+            g[2][q] = vJ ? pJ[k0 + q] : T(0);
+            g[3][q] = vJ ? zJ[k0 + q] : T(0);
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 2; ++q) {
             sZI[buf][lr][lc + q] = g[0][q];
             sPI[buf][lr][lc + q] = g[1][q];
             sPJ[buf][lr][lc + q] = g[2][q];
             sZJ[buf][lr][lc + q] = g[3][q];
         }
     };
-    v4d acc[2][2];
+    typename M::acc acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
 
-    const int nk = B.ngp / 16;
+    const int nk = B.ngp / KS;
     gload(0);
     sstore(0);
     __syncthreads();
@@ -428,9 +472,9 @@ __global__ __launch_bounds__(256) void k_syr2k(
         const int cur = ks & 1;
         if (ks + 1 < nk) gload(ks + 1);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        for (int kk = 0; kk < KS / 4; ++kk) {
             const int kc = kk * 4 + (lane >> 4);
-            double az[2], ap[2], bp[2], bz[2];
+            T az[2], ap[2], bp[2], bz[2];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb) {
                 const int r = wm * 32 + mb * 16 + (lane & 15);
@@ -447,8 +491,8 @@ __global__ __launch_bounds__(256) void k_syr2k(
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb) {
-                    acc[mb][nb] = mfma64(az[mb], bp[nb], acc[mb][nb]);
-                    acc[mb][nb] = mfma64(ap[mb], bz[nb], acc[mb][nb]);
+                    acc[mb][nb] = M::mma(az[mb], bp[nb], acc[mb][nb]);
+                    acc[mb][nb] = M::mma(ap[mb], bz[nb], acc[mb][nb]);
                 }
         }
         if (ks + 1 < nk) sstore(cur ^ 1);
@@ -458,13 +502,14 @@ __global__ __launch_bounds__(256) void k_syr2k(
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = I * kTile + wm * 32 + mb * 16 + 4 * r + (lane >> 4);
+            const int row = I * kTile + wm * 32 + mb * 16 + M::acc_row(r, lane);
             if (row >= B.nb) continue;
             double* vrow = V + (size_t)fl[row] * nbf;
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
                 const int col = J * kTile + wn * 32 + nb * 16 + (lane & 15);
-                if (col < B.nb && col <= row) unsafeAtomicAdd(vrow + fl[col], acc[mb][nb][r]);
+                if (col < B.nb && col <= row)
+                    unsafeAtomicAdd(vrow + fl[col], double(acc[mb][nb][r]));
             }
         }
     }
@@ -517,8 +562,51 @@ __global__ void k_reduce_en(const double* epart, const double* npart, long long 
 }
 
 // ------------------------------------------------------------- driver -----
-int run_integrate(xc_context* c, int functional, const double* dP, double* dV,
-                  double* dEN) {
+template <bool GGA, typename T>
+static int run_waves(xc_context* c, const double* dP, double* dV) {
+    const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
+    const int* gpre = (const int*)c->d_gemm_pre.p;
+    const int* spre = (const int*)c->d_syr_pre.p;
+    char* scr = (char*)c->scratch.p;
+    for (const Wave& w : c->waves) {
+        if (w.count == 0) continue;
+        const WaveBatch* b = wb + w.wb_off;
+        {
+            PhaseScope ps(c, XC_PHASE_COLLOC);
+            hipLaunchKernelGGL((k_colloc<GGA, T>), dim3(w.count), dim3(256), 0, c->stream, b,
+                               (const ShellDev*)c->d_shells.p, (const double*)c->d_palpha.p,
+                               (const double*)c->d_pcoef.p, (const int*)c->shell_list.p,
+                               (const int*)c->shell_loff.p, (const double*)c->px.p,
+                               (const double*)c->py.p, (const double*)c->pz.p, scr);
+            XC_HIP(hipGetLastError());
+        }
+        if (w.gemm_tiles > 0) {
+            PhaseScope ps(c, XC_PHASE_DENSITY);
+            hipLaunchKernelGGL((k_gemm_rho<GGA, T>), dim3(w.gemm_tiles), dim3(256), 0,
+                               c->stream, b, gpre + w.pre_off, w.count, w.gemm_tiles, dP,
+                               c->nbf, (const int*)c->func_list.p, scr);
+            XC_HIP(hipGetLastError());
+        }
+        {
+            PhaseScope ps(c, XC_PHASE_FUNCTIONAL);
+            hipLaunchKernelGGL((k_func_z<GGA, T>), dim3(w.count), dim3(256), 0, c->stream, b,
+                               (const double*)c->pw.p, c->rho_thresh, scr,
+                               (double*)c->epart.p, (double*)c->npart.p);
+            XC_HIP(hipGetLastError());
+        }
+        if (w.syr_tiles > 0) {
+            PhaseScope ps(c, XC_PHASE_POTENTIAL);
+            hipLaunchKernelGGL((k_syr2k<T>), dim3(w.syr_tiles), dim3(256), 0, c->stream, b,
+                               spre + w.pre_off, w.count, w.syr_tiles,
+                               (const int*)c->func_list.p, (const char*)scr, dV, c->nbf);
+            XC_HIP(hipGetLastError());
+        }
+    }
+    return XC_OK;
+}
+
+int run_integrate(xc_context* c, int functional, int precision, const double* dP,
+                  double* dV, double* dEN) {
     const bool gga = functional == XC_GGA_PBE;
     const long long nn = (long long)c->nbf * c->nbf;
     {
@@ -526,61 +614,12 @@ int run_integrate(xc_context* c, int functional, const double* dP, double* dV,
         hipLaunchKernelGGL(k_fill, dim3(grid_1d(nn, 256)), dim3(256), 0, c->stream, dV, nn, 0.0);
         XC_HIP(hipGetLastError());
     }
-    const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
-    const int* gpre = (const int*)c->d_gemm_pre.p;
-    const int* spre = (const int*)c->d_syr_pre.p;
-    double* scr = (double*)c->scratch.p;
-    for (const Wave& w : c->waves) {
-        if (w.count == 0) continue;
-        const WaveBatch* b = wb + w.wb_off;
-        {
-        PhaseScope ps(c, XC_PHASE_COLLOC);
-        if (gga)
-            hipLaunchKernelGGL(k_colloc<true>, dim3(w.count), dim3(256), 0, c->stream, b,
-                               (const ShellDev*)c->d_shells.p, (const double*)c->d_palpha.p,
-                               (const double*)c->d_pcoef.p, (const int*)c->shell_list.p,
-                               (const int*)c->shell_loff.p, (const double*)c->px.p,
-                               (const double*)c->py.p, (const double*)c->pz.p, scr);
-        else
-            hipLaunchKernelGGL(k_colloc<false>, dim3(w.count), dim3(256), 0, c->stream, b,
-                               (const ShellDev*)c->d_shells.p, (const double*)c->d_palpha.p,
-                               (const double*)c->d_pcoef.p, (const int*)c->shell_list.p,
-                               (const int*)c->shell_loff.p, (const double*)c->px.p,
-                               (const double*)c->py.p, (const double*)c->pz.p, scr);
-        XC_HIP(hipGetLastError());
-        }
-        if (w.gemm_tiles > 0) {
-            PhaseScope ps(c, XC_PHASE_DENSITY);
-            if (gga)
-                hipLaunchKernelGGL(k_gemm_rho<true>, dim3(w.gemm_tiles), dim3(256), 0,
-                                   c->stream, b, gpre + w.pre_off, w.count, w.gemm_tiles,
-                                   dP, c->nbf, (const int*)c->func_list.p, scr);
-            else
-                hipLaunchKernelGGL(k_gemm_rho<false>, dim3(w.gemm_tiles), dim3(256), 0,
-                                   c->stream, b, gpre + w.pre_off, w.count, w.gemm_tiles,
-                                   dP, c->nbf, (const int*)c->func_list.p, scr);
-            XC_HIP(hipGetLastError());
-        }
-        {
-        PhaseScope ps(c, XC_PHASE_FUNCTIONAL);
-        if (gga)
-            hipLaunchKernelGGL(k_func_z<true>, dim3(w.count), dim3(256), 0, c->stream, b,
-                               (const double*)c->pw.p, c->rho_thresh, scr,
-                               (double*)c->epart.p, (double*)c->npart.p);
-        else
-            hipLaunchKernelGGL(k_func_z<false>, dim3(w.count), dim3(256), 0, c->stream, b,
-                               (const double*)c->pw.p, c->rho_thresh, scr,
-                               (double*)c->epart.p, (double*)c->npart.p);
-        XC_HIP(hipGetLastError());
-        }
-        if (w.syr_tiles > 0) {
-            PhaseScope ps(c, XC_PHASE_POTENTIAL);
-            hipLaunchKernelGGL(k_syr2k, dim3(w.syr_tiles), dim3(256), 0, c->stream, b,
-                               spre + w.pre_off, w.count, w.syr_tiles,
-                               (const int*)c->func_list.p, (const double*)scr, dV, c->nbf);
-            XC_HIP(hipGetLastError());
-        }
-    }
+    int rc;
+    if (precision == XC_MIXED_FP32)
+        rc = gga ? run_waves<true, float>(c, dP, dV) : run_waves<false, float>(c, dP, dV);
+    else
+        rc = gga ? run_waves<true, double>(c, dP, dV) : run_waves<false, double>(c, dP, dV);
+    if (rc != XC_OK) return rc;
     PhaseScope ps(c, XC_PHASE_OTHER);
     const unsigned nt = (unsigned)((c->nbf + 15) / 16);
     hipLaunchKernelGGL(k_mirror, dim3(nt, nt), dim3(256), 0, c->stream, dV, c->nbf);

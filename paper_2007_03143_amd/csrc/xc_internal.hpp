@@ -118,6 +118,7 @@ struct xc_context {
     std::vector<double> ang;          // n_ang x 4
     double ssf_a = 0.64, screen_eta = 1e-10, rho_thresh = 1e-15;
     int batch_max = 512;
+    int batch_merge = 1;
     std::vector<int> gatoms;          // parent atoms whose grids are built
     size_t wave_budget = 0;
 
@@ -185,7 +186,7 @@ int run_batching(xc_context* c, const std::vector<long long>& atom_kept);
 int run_screening(xc_context* c);
 
 // integrate.hip
-int run_integrate(xc_context* c, int functional, const double* dP, double* dV,
-                  double* dEN);
+int run_integrate(xc_context* c, int functional, int precision, const double* dP,
+                  double* dV, double* dEN);
 
 }  // namespace xc

@@ -7,6 +7,22 @@ import numpy as np
 import oracle
 
 
+def gpu_integrate_prec(w, functional, precision, atom_mask=None, **grid_over):
+    import torch
+    from paper_2007_03143_amd import XcContext
+    from workloads import grid_spec_dict
+    ctx = XcContext(w.coords, w.mk_alpha, w.basis,
+                    grid_spec_dict(w, atom_mask=atom_mask, **grid_over))
+    try:
+        Pd = torch.from_numpy(np.ascontiguousarray(w.P)).cuda()
+        V, EN = ctx.integrate(Pd, functional, precision)
+        torch.cuda.synchronize()
+        en = EN.cpu().numpy()
+        return float(en[0]), float(en[1]), V.cpu().numpy(), ctx.stats()
+    finally:
+        ctx.close()
+
+
 def gpu_integrate(w, functional, atom_mask=None, wave_bytes=0, P=None, **grid_over):
     import torch
     from paper_2007_03143_amd import XcContext

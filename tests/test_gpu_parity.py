@@ -70,12 +70,15 @@ def test_mask_parity_and_additivity():
     assert np.abs(Va + Vb - V).max() <= 1e-12 * np.abs(V).max()
 
 
-@pytest.mark.parametrize("batch_max,wave_bytes", [(64, 0), (1024, 0), (512, 1 << 20)])
-def test_batching_and_wave_invariance(batch_max, wave_bytes):
+@pytest.mark.parametrize("batch_max,wave_bytes,merge", [(64, 0, 1), (1024, 0, 1),
+                                                        (512, 1 << 20, 1), (512, 0, 0)])
+def test_batching_and_wave_invariance(batch_max, wave_bytes, merge):
     w = cfg_water()
     E0, N0, V0, st0 = gpu_integrate(w, "pbe")
-    E, N, V, st = gpu_integrate(w, "pbe", batch_max=batch_max, wave_bytes=wave_bytes)
-    say(f"  batch_max {batch_max} waves {st['n_waves']} batches {st['n_batches']}")
+    E, N, V, st = gpu_integrate(w, "pbe", batch_max=batch_max, wave_bytes=wave_bytes,
+                                batch_merge=merge)
+    say(f"  batch_max {batch_max} merge {merge} waves {st['n_waves']} "
+        f"batches {st['n_batches']} (default {st0['n_batches']})")
     assert st["max_ng"] <= batch_max
     assert abs(E - E0) <= 1e-12 * abs(E0)
     assert np.abs(V - V0).max() <= 1e-12 * np.abs(V0).max()
@@ -162,3 +165,18 @@ def test_cluster_sampled_atoms_parity(atom):
     mask = np.zeros(w.natoms, np.uint8)
     mask[atom] = 1
     _check(w, "pbe", atom_mask=mask)
+
+
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_mixed_fp32_error_vs_oracle(functional):
+    """FP32 collocation and contractions, FP64 functional and sums: errors
+    against the FP64 oracle are reported and bounded."""
+    w = cfg_water()
+    say(f"case water {functional} fp32")
+    from gpu_util import gpu_integrate_prec
+    E, N, V, st = gpu_integrate_prec(w, functional, "fp32")
+    Eo, No, Vo = oracle_integrate(w, functional)
+    say(f"  fp32: dE {E - Eo:.3e} dN {N - No:.3e} max dV {np.abs(V - Vo).max():.3e}")
+    assert abs(E - Eo) <= 1e-5 and abs(N - No) <= 1e-5
+    assert np.abs(V - Vo).max() <= 1e-4
+    assert np.array_equal(V, V.T)

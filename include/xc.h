@@ -256,6 +256,77 @@ int xc_context_timing(xc_context* ctx, xc_timing* out);
 /* Release every device resource of the context (synchronises its stream). */
 int xc_context_destroy(xc_context* ctx);
 
+/*
+ * Continuous-batching engine. Many integrations (typically the successive
+ * SCF iterations of many molecules) share one device and one stream:
+ *  - a request is a molecule + basis + grid + functional + precision; it is
+ *    admitted when its expected device footprint fits the engine's budget
+ *    next to the already admitted requests; admission builds its grid, which
+ *    then stays on the device until the request is released (grid reuse
+ *    across Fock builds, Sec. 2.3.1);
+ *  - an integration (one P -> V, E_xc, N_e) is submitted against a request;
+ *    a request runs its integrations one at a time, in submission order;
+ *  - every step co-batches the pending grid batches of all in-flight
+ *    integrations (round-robin, one batch of each in turn, until the wave
+ *    scratch is full) into the same launches, so integrations that arrive
+ *    while others run join the next step.
+ * Device buffers passed to xc_engine_submit must stay valid until the
+ * ticket polls done. Calls on one engine must not overlap.
+ */
+typedef struct xc_engine xc_engine;
+
+typedef struct xc_engine_opts {
+    void* stream;        /* hipStream_t for all engine work (NULL: null stream) */
+    size_t hbm_budget;   /* device bytes admitted requests may hold; 0: half the free memory */
+    size_t wave_bytes;   /* scratch of one co-batched step; 0: min(free/8, 8 GiB) */
+} xc_engine_opts;
+
+typedef struct xc_engine_info {
+    int waiting;                /* requests not yet admitted */
+    int admitted;
+    int in_flight;              /* requests with an integration in progress */
+    size_t bytes_used;          /* device bytes held by admitted requests */
+    size_t budget;
+    size_t wave_bytes;
+    long long steps;
+    long long batches_launched;
+    long long completed;        /* integrations polled done */
+} xc_engine_info;
+
+/* Create an engine; allocates its wave scratch. */
+int xc_engine_create(const xc_engine_opts* opts, xc_engine** out);
+
+/* Add a request (inputs are copied). XC_ERR_NOMEM if it can never fit. */
+int xc_engine_add_request(xc_engine* eng, const xc_molecule* mol,
+                          const xc_basis* basis, const xc_grid_spec* grid,
+                          int functional, int precision, long long* req_id);
+
+/*
+ * Queue one integration of a request. d_P (read), d_V (written, nbf x nbf)
+ * and d_EN (written, 2 doubles) are device buffers owned by the caller.
+ */
+int xc_engine_submit(xc_engine* eng, long long req_id, const double* d_P,
+                     double* d_V, double* d_EN, long long* ticket);
+
+/*
+ * Admit waiting requests that fit (builds their grids; synchronises the
+ * stream while doing so), then launch one co-batched step. *n_batches (may
+ * be NULL) receives the number of batches launched.
+ */
+int xc_engine_step(xc_engine* eng, int* n_batches);
+
+/* *done = 1 once the ticket's V, E_xc and N_e are final (non-blocking). A
+ * ticket reported done is retired and cannot be polled again. */
+int xc_engine_poll(xc_engine* eng, long long ticket, int* done);
+
+/* Drop a request with no integration in flight; frees its device memory. */
+int xc_engine_release(xc_engine* eng, long long req_id);
+
+int xc_engine_stats(xc_engine* eng, xc_engine_info* out);
+
+/* Synchronise and free everything the engine holds. */
+int xc_engine_destroy(xc_engine* eng);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,6 +79,20 @@ class XcTiming(Structure):
                 for i, p in enumerate(PHASES)}
 
 
+class XcEngineOpts(Structure):
+    _fields_ = [("stream", c_void_p), ("hbm_budget", c_size_t), ("wave_bytes", c_size_t)]
+
+
+class XcEngineInfo(Structure):
+    _fields_ = [("waiting", c_int), ("admitted", c_int), ("in_flight", c_int),
+                ("bytes_used", c_size_t), ("budget", c_size_t), ("wave_bytes", c_size_t),
+                ("steps", c_longlong), ("batches_launched", c_longlong),
+                ("completed", c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class XcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (code {code})")
@@ -124,6 +138,25 @@ def _load():
     lib.xc_context_timing.argtypes = [c_void_p, POINTER(XcTiming)]
     lib.xc_context_destroy.restype = c_int
     lib.xc_context_destroy.argtypes = [c_void_p]
+    lib.xc_engine_create.restype = c_int
+    lib.xc_engine_create.argtypes = [POINTER(XcEngineOpts), POINTER(c_void_p)]
+    lib.xc_engine_add_request.restype = c_int
+    lib.xc_engine_add_request.argtypes = [c_void_p, POINTER(XcMolecule), POINTER(XcBasis),
+                                          POINTER(XcGridSpec), c_int, c_int,
+                                          POINTER(c_longlong)]
+    lib.xc_engine_submit.restype = c_int
+    lib.xc_engine_submit.argtypes = [c_void_p, c_longlong, c_void_p, c_void_p, c_void_p,
+                                     POINTER(c_longlong)]
+    lib.xc_engine_step.restype = c_int
+    lib.xc_engine_step.argtypes = [c_void_p, POINTER(c_int)]
+    lib.xc_engine_poll.restype = c_int
+    lib.xc_engine_poll.argtypes = [c_void_p, c_longlong, POINTER(c_int)]
+    lib.xc_engine_release.restype = c_int
+    lib.xc_engine_release.argtypes = [c_void_p, c_longlong]
+    lib.xc_engine_stats.restype = c_int
+    lib.xc_engine_stats.argtypes = [c_void_p, POINTER(XcEngineInfo)]
+    lib.xc_engine_destroy.restype = c_int
+    lib.xc_engine_destroy.argtypes = [c_void_p]
     return lib
 
 
@@ -257,6 +290,56 @@ def xc_context_timing(handle):
 
 def xc_context_destroy(handle):
     _check(LIB.xc_context_destroy(handle))
+
+
+def xc_engine_create(stream=0, hbm_budget=0, wave_bytes=0):
+    h = c_void_p()
+    opts = XcEngineOpts(c_void_p(int(stream)), int(hbm_budget), int(wave_bytes))
+    _check(LIB.xc_engine_create(byref(opts), byref(h)))
+    return h
+
+
+def xc_engine_add_request(handle, coords, mk_alpha, basis, grid, functional,
+                          precision="fp64"):
+    inp = _Inputs(coords, mk_alpha, basis, grid)
+    rid = c_longlong()
+    _check(LIB.xc_engine_add_request(handle, byref(inp.mol), byref(inp.basis),
+                                     byref(inp.grid), _code(FUNCTIONALS, functional),
+                                     _code(PRECISIONS, precision), byref(rid)))
+    return rid.value, inp.nbf
+
+
+def xc_engine_submit(handle, req_id, d_P, d_V, d_EN):
+    t = c_longlong()
+    _check(LIB.xc_engine_submit(handle, req_id, c_void_p(d_P), c_void_p(d_V),
+                                c_void_p(d_EN), byref(t)))
+    return t.value
+
+
+def xc_engine_step(handle):
+    n = c_int()
+    _check(LIB.xc_engine_step(handle, byref(n)))
+    return n.value
+
+
+def xc_engine_poll(handle, ticket):
+    d = c_int()
+    _check(LIB.xc_engine_poll(handle, ticket, byref(d)))
+    return bool(d.value)
+
+
+def xc_engine_release(handle, req_id):
+    _check(LIB.xc_engine_release(handle, req_id))
+
+
+def xc_engine_stats(handle):
+    s = XcEngineInfo()
+    _check(LIB.xc_engine_stats(handle, byref(s)))
+    return s.as_dict()
+
+
+def xc_engine_destroy(handle):
+    _check(LIB.xc_engine_destroy(handle))
 
 
 class XcContext:

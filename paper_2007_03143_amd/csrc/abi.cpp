@@ -72,18 +72,20 @@ static hipEvent_t take_event(PhaseTimer& t) {
     return e;
 }
 
-PhaseScope::PhaseScope(xc_context* c, int phase) : c_(c), phase_(phase) {
-    if (!c_->timer.enabled) return;
-    e0_ = take_event(c_->timer);
-    if (e0_) (void)hipEventRecord(e0_, c_->stream);
+PhaseScope::PhaseScope(xc_context* c, int phase) : PhaseScope(&c->timer, c->stream, phase) {}
+
+PhaseScope::PhaseScope(PhaseTimer* t, hipStream_t s, int phase) : t_(t), s_(s), phase_(phase) {
+    if (!t_ || !t_->enabled) return;
+    e0_ = take_event(*t_);
+    if (e0_) (void)hipEventRecord(e0_, s_);
 }
 
 PhaseScope::~PhaseScope() {
     if (!e0_) return;
-    hipEvent_t e1 = take_event(c_->timer);
+    hipEvent_t e1 = take_event(*t_);
     if (!e1) return;
-    (void)hipEventRecord(e1, c_->stream);
-    c_->timer.pending[phase_].emplace_back(e0_, e1);
+    (void)hipEventRecord(e1, s_);
+    t_->pending[phase_].emplace_back(e0_, e1);
 }
 
 static int fold_timer(xc_context* c) {
@@ -101,6 +103,30 @@ static int fold_timer(xc_context* c) {
         t.pending[p].clear();
     }
     return XC_OK;
+}
+
+void release_build_temporaries(xc_context* c) {
+    DevBuf* bufs[] = {&c->raw_x, &c->raw_y, &c->raw_z, &c->raw_w, &c->tx, &c->ty, &c->tz,
+                      &c->tw, &c->tidx, &c->blk_count, &c->blk_off, &c->atom_count,
+                      &c->cells_a, &c->cells_b, &c->child_count, &c->child_begin,
+                      &c->counters, &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff};
+    for (DevBuf* b : bufs) dev_release(*b);
+}
+
+size_t device_bytes(const xc_context* c) {
+    const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
+                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->raw_x, &c->raw_y,
+                            &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
+                            &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
+                            &c->blk_off, &c->atom_count, &c->cells_a, &c->cells_b,
+                            &c->child_count, &c->child_begin, &c->batches, &c->counters,
+                            &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
+                            &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
+                            &c->d_gemm_pre, &c->d_syr_pre, &c->scratch, &c->epart,
+                            &c->npart, &c->d_req};
+    size_t n = 0;
+    for (const DevBuf* b : bufs) n += b->cap;
+    return n;
 }
 
 static void destroy_timer(PhaseTimer& t) {
@@ -181,7 +207,8 @@ static void release_all(xc_context* c) {
                       &c->child_count, &c->child_begin, &c->batches, &c->counters,
                       &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                       &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
-                      &c->d_gemm_pre, &c->d_syr_pre, &c->scratch, &c->epart, &c->npart};
+                      &c->d_gemm_pre, &c->d_syr_pre, &c->scratch, &c->epart, &c->npart,
+                      &c->d_req};
     for (DevBuf* b : bufs) dev_release(*b);
 }
 
@@ -242,6 +269,7 @@ static int plan_waves(xc_context* c) {
         w.nmt = nmt;
         w.nshell = c->h_nsh[j];
         w.batch = (int)j;
+        w.req = 0;
         c->h_wb.push_back(w);
         used += bytes;
         const int gt = nmt * (ngp / kTile);
@@ -263,14 +291,15 @@ static int plan_waves(xc_context* c) {
                   c->stream));
     XC_TRY(upload(c->d_gemm_pre, gpre.data(), sizeof(int) * gpre.size(), c->stream));
     XC_TRY(upload(c->d_syr_pre, spre.data(), sizeof(int) * spre.size(), c->stream));
-    XC_TRY(dev_reserve(c->scratch, std::max<size_t>(c->max_wave_bytes, 8)));
+    if (!c->external_scratch)
+        XC_TRY(dev_reserve(c->scratch, std::max<size_t>(c->max_wave_bytes, 8)));
     XC_TRY(dev_reserve(c->epart, 8 * (size_t)std::max<long long>(1, c->n_batches)));
     XC_TRY(dev_reserve(c->npart, 8 * (size_t)std::max<long long>(1, c->n_batches)));
     XC_HIP(hipStreamSynchronize(c->stream));
     return XC_OK;
 }
 
-static int build_grid(xc_context* c) {
+int build_grid(xc_context* c) {
     c->built = false;
     const long long npa = (long long)c->n_rad * c->n_ang;
     c->n_nominal = npa * (long long)c->gatoms.size();

@@ -1,0 +1,408 @@
+// Continuous-batching engine: many XC integrations (one per SCF iteration of
+// many molecules) share the device. Requests are admitted by device-memory
+// footprint; an admitted request's grid, weights, batches and screening
+// lists stay on the device across its iterations (grid reuse, Sec. 2.3.1);
+// every step co-batches the pending grid batches of all in-flight
+// integrations into the same four launches (Alg. 4 over a mixed batch set).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "xc_internal.hpp"
+
+namespace xc {
+
+struct Integration {
+    long long ticket = 0;
+    long long req = 0;
+    const double* P = nullptr;
+    double* V = nullptr;
+    double* EN = nullptr;
+    long long next_batch = 0;
+    bool started = false;
+    bool launched_finish = false;
+    hipEvent_t done = nullptr;
+};
+
+struct Request {
+    long long id = 0;
+    xc_context* ctx = nullptr;
+    int functional = XC_GGA_PBE;
+    int precision = XC_FP64;
+    size_t est_bytes = 0;
+    size_t bytes = 0;
+    bool admitted = false;
+    bool released = false;
+    std::deque<Integration*> queued;
+    Integration* active = nullptr;
+};
+
+}  // namespace xc
+
+struct xc_engine {
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    size_t wave_bytes = 0;
+    size_t used = 0;
+    xc::DevBuf scratch, d_wb, d_gpre, d_spre, d_reqs;
+    std::map<long long, xc::Request*> reqs;
+    std::deque<long long> waiting;
+    std::map<long long, xc::Integration*> tickets;
+    long long next_req = 1, next_ticket = 1;
+    long long steps = 0, batches_launched = 0, completed = 0;
+    xc::PhaseTimer timer;
+};
+
+namespace xc {
+
+int build_grid(xc_context* c);
+
+static size_t batch_bytes(const WaveBatch& w) {
+    return 8 * (4 * (size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
+}
+
+// Device bytes an unbuilt context is expected to need while it is built and
+// afterwards (points, weights and temporaries scale with the nominal grid;
+// screening lists with points x basis size).
+static size_t estimate_bytes(const xc_context* c) {
+    const double npts = (double)c->n_rad * c->n_ang * (double)c->gatoms.size();
+    const double build = npts * (32.0 + 80.0 + 8.0);
+    const double lists = npts / 64.0 * (8.0 + 8.0 * std::min(c->nbf, 4096));
+    const double fixed = 8.0 * c->natoms * (double)c->natoms + 4096.0 * 1024.0;
+    return (size_t)(build + lists + fixed);
+}
+
+static int admit(xc_engine* e) {
+    for (auto it = e->waiting.begin(); it != e->waiting.end();) {
+        Request* r = e->reqs[*it];
+        if (r->released) {
+            it = e->waiting.erase(it);
+            continue;
+        }
+        if (e->used + r->est_bytes > e->budget) {
+            ++it;
+            continue;
+        }
+        r->ctx->external_scratch = true;
+        int rc = build_grid(r->ctx);
+        if (rc != XC_OK) return rc;
+        release_build_temporaries(r->ctx);
+        r->bytes = device_bytes(r->ctx);
+        e->used += r->bytes;
+        r->admitted = true;
+        for (const WaveBatch& w : r->ctx->h_wb)
+            if (batch_bytes(w) > e->wave_bytes)
+                return fail(XC_ERR_NOMEM, "a batch is larger than the engine's wave scratch");
+        it = e->waiting.erase(it);
+    }
+    return XC_OK;
+}
+
+static void destroy_request(xc_engine* e, Request* r) {
+    if (r->ctx) {
+        xc_context_destroy(r->ctx);
+        r->ctx = nullptr;
+    }
+    if (r->admitted) e->used -= std::min(e->used, r->bytes);
+    r->admitted = false;
+}
+
+struct Group {
+    std::vector<WaveBatch> wb;
+    std::vector<int> gpre{0}, spre{0};
+    std::vector<ReqDev> rd;
+    std::map<Integration*, int> slot;
+    int gemm = 0, syr = 0;
+};
+
+static int engine_step(xc_engine* e, int* launched) {
+    *launched = 0;
+    XC_TRY(admit(e));
+    // activate the next queued integration of every admitted request
+    std::vector<Integration*> act;
+    for (auto& kv : e->reqs) {
+        Request* r = kv.second;
+        if (!r->admitted) continue;
+        if (!r->active && !r->queued.empty()) {
+            r->active = r->queued.front();
+            r->queued.pop_front();
+        }
+        if (r->active && !r->active->launched_finish) act.push_back(r->active);
+    }
+    std::sort(act.begin(), act.end(),
+              [](const Integration* a, const Integration* b) { return a->ticket < b->ticket; });
+    if (act.empty()) return XC_OK;
+    // zero V of integrations that start now
+    for (Integration* in : act) {
+        if (in->started) continue;
+        const int nbf = e->reqs[in->req]->ctx->nbf;
+        const long long nn = (long long)nbf * nbf;
+        XC_TRY(launch_fill(e->stream, in->V, nn, 0.0));
+        in->started = true;
+    }
+    // round-robin: one batch of each in-flight integration at a time until the
+    // wave scratch is full or every integration is exhausted
+    std::map<int, Group> groups;  // key: precision * 2 + gga
+    size_t used = 0;
+    bool progress = true;
+    while (progress) {
+        progress = false;
+        for (Integration* in : act) {
+            Request* r = e->reqs[in->req];
+            xc_context* c = r->ctx;
+            if (in->next_batch >= c->n_batches) continue;
+            WaveBatch w = c->h_wb[in->next_batch];
+            const size_t bytes = batch_bytes(w);
+            if (used + bytes > e->wave_bytes) continue;
+            const int key = r->precision * 2 + (r->functional == XC_GGA_PBE ? 1 : 0);
+            Group& g = groups[key];
+            auto sl = g.slot.find(in);
+            int req_slot;
+            if (sl == g.slot.end()) {
+                req_slot = (int)g.rd.size();
+                g.slot[in] = req_slot;
+                g.rd.push_back(make_req(c, in->P, in->V));
+            } else {
+                req_slot = sl->second;
+            }
+            w.phi_off = (long long)(used / 8);
+            w.part_off = (long long)(used / 8 + 4 * (size_t)w.nbp * w.ngp);
+            w.req = req_slot;
+            used += bytes;
+            const int gt = w.nmt * (w.ngp / kTile);
+            const int st = w.nmt * (w.nmt + 1) / 2;
+            g.wb.push_back(w);
+            g.gpre.push_back(g.gpre.back() + gt);
+            g.spre.push_back(g.spre.back() + st);
+            g.gemm += gt;
+            g.syr += st;
+            in->next_batch += 1;
+            *launched += 1;
+            progress = true;
+        }
+    }
+    // upload the descriptors of every group (one array each, groups back to back)
+    std::vector<WaveBatch> all_wb;
+    std::vector<int> all_g, all_s;
+    std::vector<ReqDev> all_rd;
+    struct Off { size_t wb, pre, rd; };
+    std::map<int, Off> offs;
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        Off o{all_wb.size(), all_g.size(), all_rd.size()};
+        for (WaveBatch& w : g.wb) w.req += (int)o.rd;
+        offs[kv.first] = o;
+        all_wb.insert(all_wb.end(), g.wb.begin(), g.wb.end());
+        all_g.insert(all_g.end(), g.gpre.begin(), g.gpre.end());
+        all_s.insert(all_s.end(), g.spre.begin(), g.spre.end());
+        all_rd.insert(all_rd.end(), g.rd.begin(), g.rd.end());
+    }
+    if (!all_wb.empty()) {
+        // growing a descriptor buffer frees the old one: let earlier steps that
+        // read it finish first
+        const size_t need[4] = {sizeof(WaveBatch) * all_wb.size(), sizeof(int) * all_g.size(),
+                                sizeof(int) * all_s.size(), sizeof(ReqDev) * all_rd.size()};
+        const DevBuf* bufs[4] = {&e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs};
+        for (int q = 0; q < 4; ++q) {
+            if (bufs[q]->cap < need[q]) {
+                XC_HIP(hipStreamSynchronize(e->stream));
+                break;
+            }
+        }
+        XC_TRY(dev_reserve(e->d_wb, 2 * need[0]));
+        XC_TRY(dev_reserve(e->d_gpre, 2 * need[1]));
+        XC_TRY(dev_reserve(e->d_spre, 2 * need[2]));
+        XC_TRY(dev_reserve(e->d_reqs, 2 * need[3]));
+        XC_TRY(upload(e->d_wb, all_wb.data(), sizeof(WaveBatch) * all_wb.size(), e->stream));
+        XC_TRY(upload(e->d_gpre, all_g.data(), sizeof(int) * all_g.size(), e->stream));
+        XC_TRY(upload(e->d_spre, all_s.data(), sizeof(int) * all_s.size(), e->stream));
+        XC_TRY(upload(e->d_reqs, all_rd.data(), sizeof(ReqDev) * all_rd.size(), e->stream));
+        for (auto& kv : groups) {
+            const Group& g = kv.second;
+            const Off& o = offs[kv.first];
+            const int precision = kv.first / 2;
+            const bool gga = kv.first & 1;
+            XC_TRY(launch_wave(&e->timer, e->stream, gga, precision,
+                               (const WaveBatch*)e->d_wb.p + o.wb,
+                               (const int*)e->d_gpre.p + o.pre,
+                               (const int*)e->d_spre.p + o.pre, (int)g.wb.size(), g.gemm,
+                               g.syr, (const ReqDev*)e->d_reqs.p, (char*)e->scratch.p));
+        }
+        e->batches_launched += *launched;
+    }
+    // finish integrations whose last batch has been launched
+    for (Integration* in : act) {
+        Request* r = e->reqs[in->req];
+        xc_context* c = r->ctx;
+        if (in->next_batch < c->n_batches || in->launched_finish) continue;
+        XC_TRY(launch_finish(&e->timer, e->stream, in->V, c->nbf, (const double*)c->epart.p,
+                             (const double*)c->npart.p, c->n_batches, in->EN));
+        XC_HIP(hipEventCreateWithFlags(&in->done, hipEventDisableTiming));
+        XC_HIP(hipEventRecord(in->done, e->stream));
+        in->launched_finish = true;
+        r->active = nullptr;
+    }
+    e->steps += 1;
+    return XC_OK;
+}
+
+}  // namespace xc
+
+using namespace xc;
+
+extern "C" {
+
+int xc_engine_create(const xc_engine_opts* opts, xc_engine** out) {
+    if (!out) return fail(XC_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    xc_engine* e = new (std::nothrow) xc_engine();
+    if (!e) return fail(XC_ERR_NOMEM, "host allocation failed");
+    e->stream = opts ? (hipStream_t)opts->stream : nullptr;
+    size_t fr = 0, tot = 0;
+    hipError_t st = hipMemGetInfo(&fr, &tot);
+    if (st != hipSuccess) {
+        delete e;
+        return hip_fail(st, "hipMemGetInfo");
+    }
+    e->wave_bytes = (opts && opts->wave_bytes) ? opts->wave_bytes
+                                               : std::min<size_t>(fr / 8, (size_t)8 << 30);
+    e->budget = (opts && opts->hbm_budget) ? opts->hbm_budget : fr / 2;
+    int rc = dev_reserve(e->scratch, e->wave_bytes);
+    if (rc != XC_OK) {
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return XC_OK;
+}
+
+int xc_engine_add_request(xc_engine* e, const xc_molecule* mol, const xc_basis* basis,
+                          const xc_grid_spec* grid, int functional, int precision,
+                          long long* req_id) {
+    if (!e || !req_id) return fail(XC_ERR_INVALID_ARG, "null engine or output");
+    if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE)
+        return fail(XC_ERR_UNSUPPORTED, "unknown functional");
+    if (precision != XC_FP64 && precision != XC_MIXED_FP32)
+        return fail(XC_ERR_UNSUPPORTED, "precision not available");
+    xc_device_opts o{e->stream, 0};
+    xc_context* c = nullptr;
+    XC_TRY(xc_context_create(mol, basis, grid, &o, &c));
+    Request* r = new (std::nothrow) Request();
+    if (!r) {
+        xc_context_destroy(c);
+        return fail(XC_ERR_NOMEM, "host allocation failed");
+    }
+    r->id = e->next_req++;
+    r->ctx = c;
+    r->functional = functional;
+    r->precision = precision;
+    r->est_bytes = estimate_bytes(c);
+    if (r->est_bytes > e->budget) {
+        xc_context_destroy(c);
+        delete r;
+        return fail(XC_ERR_NOMEM, "request larger than the engine's memory budget");
+    }
+    e->reqs[r->id] = r;
+    e->waiting.push_back(r->id);
+    *req_id = r->id;
+    return XC_OK;
+}
+
+int xc_engine_submit(xc_engine* e, long long req_id, const double* d_P, double* d_V,
+                     double* d_EN, long long* ticket) {
+    if (!e || !ticket || !d_P || !d_V || !d_EN)
+        return fail(XC_ERR_INVALID_ARG, "null engine, buffer or output");
+    auto it = e->reqs.find(req_id);
+    if (it == e->reqs.end() || it->second->released)
+        return fail(XC_ERR_INVALID_ARG, "unknown or released request");
+    Integration* in = new (std::nothrow) Integration();
+    if (!in) return fail(XC_ERR_NOMEM, "host allocation failed");
+    in->ticket = e->next_ticket++;
+    in->req = req_id;
+    in->P = d_P;
+    in->V = d_V;
+    in->EN = d_EN;
+    it->second->queued.push_back(in);
+    e->tickets[in->ticket] = in;
+    *ticket = in->ticket;
+    return XC_OK;
+}
+
+int xc_engine_step(xc_engine* e, int* n_batches) {
+    if (!e) return fail(XC_ERR_INVALID_ARG, "null engine");
+    int dummy = 0;
+    return engine_step(e, n_batches ? n_batches : &dummy);
+}
+
+int xc_engine_poll(xc_engine* e, long long ticket, int* done) {
+    if (!e || !done) return fail(XC_ERR_INVALID_ARG, "null engine or output");
+    auto it = e->tickets.find(ticket);
+    if (it == e->tickets.end()) return fail(XC_ERR_INVALID_ARG, "unknown ticket");
+    Integration* in = it->second;
+    *done = 0;
+    if (!in->done) return XC_OK;
+    hipError_t q = hipEventQuery(in->done);
+    if (q == hipErrorNotReady) return XC_OK;
+    if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    *done = 1;
+    (void)hipEventDestroy(in->done);
+    e->tickets.erase(it);
+    delete in;
+    e->completed += 1;
+    return XC_OK;
+}
+
+int xc_engine_release(xc_engine* e, long long req_id) {
+    if (!e) return fail(XC_ERR_INVALID_ARG, "null engine");
+    auto it = e->reqs.find(req_id);
+    if (it == e->reqs.end()) return fail(XC_ERR_INVALID_ARG, "unknown request");
+    Request* r = it->second;
+    if (r->active || !r->queued.empty())
+        return fail(XC_ERR_STATE, "request still has integrations in flight");
+    r->released = true;
+    destroy_request(e, r);
+    e->reqs.erase(it);
+    delete r;
+    return XC_OK;
+}
+
+int xc_engine_stats(xc_engine* e, xc_engine_info* s) {
+    if (!e || !s) return fail(XC_ERR_INVALID_ARG, "null engine or stats");
+    std::memset(s, 0, sizeof(*s));
+    for (auto& kv : e->reqs) {
+        if (kv.second->admitted) s->admitted += 1;
+        else s->waiting += 1;
+        if (kv.second->active) s->in_flight += 1;
+    }
+    s->bytes_used = e->used;
+    s->budget = e->budget;
+    s->wave_bytes = e->wave_bytes;
+    s->steps = e->steps;
+    s->batches_launched = e->batches_launched;
+    s->completed = e->completed;
+    return XC_OK;
+}
+
+int xc_engine_destroy(xc_engine* e) {
+    if (!e) return XC_OK;
+    (void)hipStreamSynchronize(e->stream);
+    for (auto& kv : e->tickets) {
+        if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+        delete kv.second;
+    }
+    for (auto& kv : e->reqs) {
+        destroy_request(e, kv.second);
+        delete kv.second;
+    }
+    DevBuf* bufs[] = {&e->scratch, &e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs};
+    for (DevBuf* b : bufs) dev_release(*b);
+    delete e;
+    return XC_OK;
+}
+
+}  // extern "C"

@@ -19,10 +19,6 @@
 #include "functional.hpp"
 #include "xc_internal.hpp"
 
-// Accumulator row of register r in lane l for the FP32 16x16x4 MFMA.
-#ifndef XC_F32_ACC_ROW
-#define XC_F32_ACC_ROW(r, lane) (4 * (r) + ((lane) >> 4))
-#endif
 
 namespace xc {
 
@@ -32,7 +28,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // 16x16x4 MFMA of the storage type: FP64 (v_mfma_f64_16x16x4f64) or FP32
 // (v_mfma_f32_16x16x4f32). Operand lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register r of lane l holds C[row][l % 16]
-// with row = acc_row(r, l).
+// with row = acc_row(r, l): 4 r + l / 16 for FP64 but 4 (l / 16) + r for
+// FP32 (both checked on gfx950).
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
     using acc = v4d;
@@ -48,7 +45,7 @@ template <> struct Mfma<float> {
     __device__ static inline acc mma(float a, float b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    __device__ static inline int acc_row(int r, int lane) { return XC_F32_ACC_ROW(r, lane); }
+    __device__ static inline int acc_row(int r, int lane) { return 4 * (lane >> 4) + r; }
 };
 
 // ------------------------------------------------------------ collocation --
@@ -102,13 +99,19 @@ __device__ inline void colloc_shell(T dx, T dy, T dz, T rad, T drad, bool live, 
 // batch's screened list, one lane per point, so a wave never diverges on
 // the contraction length. Points of the batch are staged in LDS.
 template <bool GGA, typename T>
-__global__ __launch_bounds__(256) void k_colloc(
-    const WaveBatch* __restrict__ wb, const ShellDev* __restrict__ shells,
-    const double* __restrict__ palpha, const double* __restrict__ pcoef,
-    const int* __restrict__ shell_list, const int* __restrict__ shell_loff,
-    const double* __restrict__ X, const double* __restrict__ Y,
-    const double* __restrict__ Z, char* __restrict__ scratch) {
+__global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb,
+                                                const ReqDev* __restrict__ reqs,
+                                                char* __restrict__ scratch) {
     const WaveBatch B = wb[blockIdx.x];
+    const ReqDev R = reqs[B.req];
+    const ShellDev* __restrict__ shells = R.shells;
+    const double* __restrict__ palpha = R.palpha;
+    const double* __restrict__ pcoef = R.pcoef;
+    const int* __restrict__ shell_list = R.shell_list;
+    const int* __restrict__ shell_loff = R.shell_loff;
+    const double* __restrict__ X = R.px;
+    const double* __restrict__ Y = R.py;
+    const double* __restrict__ Z = R.pz;
     __shared__ double sx[kMaxBatch], sy[kMaxBatch], sz[kMaxBatch];
     for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
         const bool v = i < B.ng;
@@ -176,12 +179,15 @@ __global__ __launch_bounds__(256) void k_colloc(
 template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_gemm_rho(
     const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
-    int ntiles, const double* __restrict__ P, int nbf,
-    const int* __restrict__ func_list, char* __restrict__ scratch) {
+    int ntiles, const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
     using M = Mfma<T>;
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int bi = find_segment(prefix, nwb, t);
     const WaveBatch B = wb[bi];
+    const ReqDev& R = reqs[B.req];
+    const double* __restrict__ P = R.P;
+    const int nbf = R.nbf;
+    const int* __restrict__ func_list = R.func_list;
     const int lt = t - prefix[bi];
     const int ntn = B.ngp / kTile;
     const int mt = lt / ntn, nt = lt - mt * ntn;
@@ -321,11 +327,15 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 
 // ------------------------------------------------- functional + Z matrix --
 template <bool GGA, typename T>
-__global__ __launch_bounds__(256) void k_func_z(
-    const WaveBatch* __restrict__ wb, const double* __restrict__ W, double rho_thresh,
-    char* __restrict__ scratch, double* __restrict__ epart,
-    double* __restrict__ npart) {
+__global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb,
+                                                const ReqDev* __restrict__ reqs,
+                                                char* __restrict__ scratch) {
     const WaveBatch B = wb[blockIdx.x];
+    const ReqDev& R = reqs[B.req];
+    const double* __restrict__ W = R.pw;
+    const double rho_thresh = R.rho_thresh;
+    double* __restrict__ epart = R.epart;
+    double* __restrict__ npart = R.npart;
     __shared__ double sa[kMaxBatch], sbx[kMaxBatch], sby[kMaxBatch], sbz[kMaxBatch];
     __shared__ double red[256];
     const double* part = (const double*)(scratch + 8 * B.part_off);
@@ -406,12 +416,15 @@ __global__ __launch_bounds__(256) void k_func_z(
 template <typename T>
 __global__ __launch_bounds__(256) void k_syr2k(
     const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
-    int ntiles, const int* __restrict__ func_list, const char* __restrict__ scratch,
-    double* __restrict__ V, int nbf) {
+    int ntiles, const ReqDev* __restrict__ reqs, const char* __restrict__ scratch) {
     using M = Mfma<T>;
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int bi = find_segment(prefix, nwb, t);
     const WaveBatch B = wb[bi];
+    const ReqDev& R = reqs[B.req];
+    const int* __restrict__ func_list = R.func_list;
+    double* __restrict__ V = R.V;
+    const int nbf = R.nbf;
     const int lt = t - prefix[bi];
     int I = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= lt) ++I;
@@ -563,46 +576,90 @@ __global__ void k_reduce_en(const double* epart, const double* npart, long long 
 
 // ------------------------------------------------------------- driver -----
 template <bool GGA, typename T>
-static int run_waves(xc_context* c, const double* dP, double* dV) {
-    const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
-    const int* gpre = (const int*)c->d_gemm_pre.p;
-    const int* spre = (const int*)c->d_syr_pre.p;
-    char* scr = (char*)c->scratch.p;
-    for (const Wave& w : c->waves) {
-        if (w.count == 0) continue;
-        const WaveBatch* b = wb + w.wb_off;
-        {
-            PhaseScope ps(c, XC_PHASE_COLLOC);
-            hipLaunchKernelGGL((k_colloc<GGA, T>), dim3(w.count), dim3(256), 0, c->stream, b,
-                               (const ShellDev*)c->d_shells.p, (const double*)c->d_palpha.p,
-                               (const double*)c->d_pcoef.p, (const int*)c->shell_list.p,
-                               (const int*)c->shell_loff.p, (const double*)c->px.p,
-                               (const double*)c->py.p, (const double*)c->pz.p, scr);
-            XC_HIP(hipGetLastError());
-        }
-        if (w.gemm_tiles > 0) {
-            PhaseScope ps(c, XC_PHASE_DENSITY);
-            hipLaunchKernelGGL((k_gemm_rho<GGA, T>), dim3(w.gemm_tiles), dim3(256), 0,
-                               c->stream, b, gpre + w.pre_off, w.count, w.gemm_tiles, dP,
-                               c->nbf, (const int*)c->func_list.p, scr);
-            XC_HIP(hipGetLastError());
-        }
-        {
-            PhaseScope ps(c, XC_PHASE_FUNCTIONAL);
-            hipLaunchKernelGGL((k_func_z<GGA, T>), dim3(w.count), dim3(256), 0, c->stream, b,
-                               (const double*)c->pw.p, c->rho_thresh, scr,
-                               (double*)c->epart.p, (double*)c->npart.p);
-            XC_HIP(hipGetLastError());
-        }
-        if (w.syr_tiles > 0) {
-            PhaseScope ps(c, XC_PHASE_POTENTIAL);
-            hipLaunchKernelGGL((k_syr2k<T>), dim3(w.syr_tiles), dim3(256), 0, c->stream, b,
-                               spre + w.pre_off, w.count, w.syr_tiles,
-                               (const int*)c->func_list.p, (const char*)scr, dV, c->nbf);
-            XC_HIP(hipGetLastError());
-        }
+static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
+                         const int* gpre, const int* spre, int count, int gemm_tiles,
+                         int syr_tiles, const ReqDev* reqs, char* scr) {
+    {
+        PhaseScope ps(timer, s, XC_PHASE_COLLOC);
+        hipLaunchKernelGGL((k_colloc<GGA, T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        XC_HIP(hipGetLastError());
+    }
+    if (gemm_tiles > 0) {
+        PhaseScope ps(timer, s, XC_PHASE_DENSITY);
+        hipLaunchKernelGGL((k_gemm_rho<GGA, T>), dim3(gemm_tiles), dim3(256), 0, s, b, gpre,
+                           count, gemm_tiles, reqs, scr);
+        XC_HIP(hipGetLastError());
+    }
+    {
+        PhaseScope ps(timer, s, XC_PHASE_FUNCTIONAL);
+        hipLaunchKernelGGL((k_func_z<GGA, T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        XC_HIP(hipGetLastError());
+    }
+    if (syr_tiles > 0) {
+        PhaseScope ps(timer, s, XC_PHASE_POTENTIAL);
+        hipLaunchKernelGGL((k_syr2k<T>), dim3(syr_tiles), dim3(256), 0, s, b, spre, count,
+                           syr_tiles, reqs, (const char*)scr);
+        XC_HIP(hipGetLastError());
     }
     return XC_OK;
+}
+
+int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
+                const WaveBatch* d_wb, const int* d_gpre, const int* d_spre, int count,
+                int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch) {
+    if (count == 0) return XC_OK;
+    if (precision == XC_MIXED_FP32)
+        return gga ? launch_wave_t<true, float>(timer, s, d_wb, d_gpre, d_spre, count,
+                                                gemm_tiles, syr_tiles, d_reqs, scratch)
+                   : launch_wave_t<false, float>(timer, s, d_wb, d_gpre, d_spre, count,
+                                                 gemm_tiles, syr_tiles, d_reqs, scratch);
+    return gga ? launch_wave_t<true, double>(timer, s, d_wb, d_gpre, d_spre, count,
+                                             gemm_tiles, syr_tiles, d_reqs, scratch)
+               : launch_wave_t<false, double>(timer, s, d_wb, d_gpre, d_spre, count,
+                                              gemm_tiles, syr_tiles, d_reqs, scratch);
+}
+
+int launch_finish(PhaseTimer* timer, hipStream_t s, double* dV, int nbf,
+                  const double* epart, const double* npart, long long nbatch,
+                  double* dEN) {
+    PhaseScope ps(timer, s, XC_PHASE_OTHER);
+    const unsigned nt = (unsigned)((nbf + 15) / 16);
+    hipLaunchKernelGGL(k_mirror, dim3(nt, nt), dim3(256), 0, s, dV, nbf);
+    XC_HIP(hipGetLastError());
+    if (nbatch > 0)
+        hipLaunchKernelGGL(k_reduce_en, dim3(1), dim3(256), 0, s, epart, npart, nbatch, dEN);
+    else
+        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, dEN, 2LL, 0.0);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
+int launch_fill(hipStream_t s, double* p, long long n, double v) {
+    if (n <= 0) return XC_OK;
+    hipLaunchKernelGGL(k_fill, dim3(grid_1d(n, 256)), dim3(256), 0, s, p, n, v);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
+ReqDev make_req(const xc_context* c, const double* dP, double* dV) {
+    ReqDev r{};
+    r.shells = (const ShellDev*)c->d_shells.p;
+    r.palpha = (const double*)c->d_palpha.p;
+    r.pcoef = (const double*)c->d_pcoef.p;
+    r.shell_list = (const int*)c->shell_list.p;
+    r.shell_loff = (const int*)c->shell_loff.p;
+    r.func_list = (const int*)c->func_list.p;
+    r.px = (const double*)c->px.p;
+    r.py = (const double*)c->py.p;
+    r.pz = (const double*)c->pz.p;
+    r.pw = (const double*)c->pw.p;
+    r.P = dP;
+    r.V = dV;
+    r.epart = (double*)c->epart.p;
+    r.npart = (double*)c->npart.p;
+    r.rho_thresh = c->rho_thresh;
+    r.nbf = c->nbf;
+    return r;
 }
 
 int run_integrate(xc_context* c, int functional, int precision, const double* dP,
@@ -614,25 +671,17 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
         hipLaunchKernelGGL(k_fill, dim3(grid_1d(nn, 256)), dim3(256), 0, c->stream, dV, nn, 0.0);
         XC_HIP(hipGetLastError());
     }
-    int rc;
-    if (precision == XC_MIXED_FP32)
-        rc = gga ? run_waves<true, float>(c, dP, dV) : run_waves<false, float>(c, dP, dV);
-    else
-        rc = gga ? run_waves<true, double>(c, dP, dV) : run_waves<false, double>(c, dP, dV);
-    if (rc != XC_OK) return rc;
-    PhaseScope ps(c, XC_PHASE_OTHER);
-    const unsigned nt = (unsigned)((c->nbf + 15) / 16);
-    hipLaunchKernelGGL(k_mirror, dim3(nt, nt), dim3(256), 0, c->stream, dV, c->nbf);
-    XC_HIP(hipGetLastError());
-    if (c->n_batches > 0) {
-        hipLaunchKernelGGL(k_reduce_en, dim3(1), dim3(256), 0, c->stream,
-                           (const double*)c->epart.p, (const double*)c->npart.p,
-                           c->n_batches, dEN);
-    } else {
-        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, c->stream, dEN, 2LL, 0.0);
-    }
-    XC_HIP(hipGetLastError());
-    return XC_OK;
+    const ReqDev req = make_req(c, dP, dV);
+    XC_TRY(upload(c->d_req, &req, sizeof(ReqDev), c->stream));
+    const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
+    const int* gpre = (const int*)c->d_gemm_pre.p;
+    const int* spre = (const int*)c->d_syr_pre.p;
+    for (const Wave& w : c->waves)
+        XC_TRY(launch_wave(&c->timer, c->stream, gga, precision, wb + w.wb_off,
+                           gpre + w.pre_off, spre + w.pre_off, w.count, w.gemm_tiles,
+                           w.syr_tiles, (const ReqDev*)c->d_req.p, (char*)c->scratch.p));
+    return launch_finish(&c->timer, c->stream, dV, c->nbf, (const double*)c->epart.p,
+                         (const double*)c->npart.p, c->n_batches, dEN);
 }
 
 }  // namespace xc

@@ -71,7 +71,29 @@ struct WaveBatch {
     int ngp;            // n_g padded to kColPad
     int nmt;            // row tiles: ceil(n_b / kTile)
     int nshell;
-    int batch;          // global batch index
+    int batch;          // batch index within its request
+    int req;            // index of the request descriptor (ReqDev) of the launch
+};
+
+// Everything a launch needs about the request (context + one integration)
+// a batch belongs to; a launch may mix batches of many requests.
+struct ReqDev {
+    const ShellDev* shells;
+    const double* palpha;
+    const double* pcoef;
+    const int* shell_list;
+    const int* shell_loff;
+    const int* func_list;
+    const double* px;
+    const double* py;
+    const double* pz;
+    const double* pw;
+    const double* P;
+    double* V;
+    double* epart;
+    double* npart;
+    double rho_thresh;
+    int nbf;
     int pad_;
 };
 
@@ -147,6 +169,8 @@ struct xc_context {
     xc::DevBuf scratch;
     size_t max_wave_bytes = 0;
     xc::DevBuf epart, npart;
+    xc::DevBuf d_req;            // one ReqDev for the context's own integrations
+    bool external_scratch = false;  // wave scratch supplied by an engine
 
     xc::PhaseTimer timer;
 
@@ -162,10 +186,12 @@ namespace xc {
 class PhaseScope {
   public:
     PhaseScope(xc_context* c, int phase);
+    PhaseScope(PhaseTimer* t, hipStream_t s, int phase);
     ~PhaseScope();
 
   private:
-    xc_context* c_;
+    PhaseTimer* t_;
+    hipStream_t s_;
     int phase_;
     hipEvent_t e0_ = nullptr;
 };
@@ -174,6 +200,11 @@ class PhaseScope {
 int dev_reserve(DevBuf& b, size_t bytes);
 void dev_release(DevBuf& b);
 int upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s);
+
+// abi.cpp
+int build_grid(xc_context* c);
+void release_build_temporaries(xc_context* c);
+size_t device_bytes(const xc_context* c);
 
 // grid.hip
 int launch_shell_setup(xc_context* c);
@@ -188,5 +219,19 @@ int run_screening(xc_context* c);
 // integrate.hip
 int run_integrate(xc_context* c, int functional, int precision, const double* dP,
                   double* dV, double* dEN);
+// Request descriptor of an integration of context c with the given buffers.
+ReqDev make_req(const xc_context* c, const double* dP, double* dV);
+// The four per-wave launches (collocation, density, functional + Z,
+// potential) over count batches whose descriptors are already on the device.
+int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
+                const WaveBatch* d_wb, const int* d_gpre, const int* d_spre,
+                int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
+                char* scratch);
+// Fill n doubles with v (a kernel, so it can be captured in a graph).
+int launch_fill(hipStream_t s, double* p, long long n, double v);
+// V mirror and the fixed-order E_xc / N_e sums of one finished integration.
+int launch_finish(PhaseTimer* timer, hipStream_t s, double* dV, int nbf,
+                  const double* epart, const double* npart, long long nbatch,
+                  double* dEN);
 
 }  // namespace xc

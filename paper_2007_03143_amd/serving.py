@@ -1,0 +1,151 @@
+"""Request loop over the continuous-batching engine of the C ABI.
+
+Requests (molecules with a sequence of SCF densities) arrive over time; each
+is added to the engine, which admits it when its device footprint fits and
+then keeps its grid on the device while its integrations run one after the
+other. Every loop turn calls one engine step, which co-batches the pending
+grid batches of all in-flight integrations, and polls the tickets. Latency of
+an integration is submit -> done as seen by this loop; throughput counts
+nominal grid points of finished integrations per second of wall time.
+
+The loop is argument marshalling and bookkeeping only: grid builds and all
+integration work run in the library's HIP kernels.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import binding as B
+
+
+@dataclass
+class ServeRequest:
+    coords: np.ndarray
+    mk_alpha: np.ndarray
+    basis: object
+    grid: dict
+    functional: str
+    densities: list            # host (nbf, nbf) arrays, one per SCF iteration
+    arrival: float = 0.0       # seconds after the start of the stream
+    precision: str = "fp64"
+    name: str = ""
+    n_points_nominal: int = 0
+    # filled in by the loop
+    req_id: int = -1
+    k: int = 0
+    results: list = field(default_factory=list)    # (E, N, V or None)
+    int_latency: list = field(default_factory=list)
+    t_done: float = 0.0
+
+
+class XcEngine:
+    """Thin owner of an engine handle and its torch buffers."""
+
+    def __init__(self, hbm_budget=0, wave_bytes=0, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = B.xc_engine_create(self.stream.cuda_stream, hbm_budget, wave_bytes)
+
+    def add(self, r):
+        rid, nbf = B.xc_engine_add_request(self.handle, r.coords, r.mk_alpha, r.basis,
+                                           r.grid, r.functional, r.precision)
+        return rid, nbf
+
+    def submit(self, rid, P, V, EN):
+        return B.xc_engine_submit(self.handle, rid, P.data_ptr(), V.data_ptr(),
+                                  EN.data_ptr())
+
+    def step(self):
+        return B.xc_engine_step(self.handle)
+
+    def poll(self, ticket):
+        return B.xc_engine_poll(self.handle, ticket)
+
+    def release(self, rid):
+        B.xc_engine_release(self.handle, rid)
+
+    def stats(self):
+        return B.xc_engine_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            B.xc_engine_destroy(self.handle)
+            self.handle = None
+
+
+def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None):
+    """Run the request stream; returns a summary dict. keep_v(i) -> bool selects
+    requests whose V matrices are copied back (for accuracy checks)."""
+    import torch
+    eng = XcEngine(hbm_budget, wave_bytes)
+    order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
+    nxt = 0
+    inflight = {}      # ticket -> (request index, submit time, P, V, EN)
+    n_done_int = 0
+    points_done = 0
+    t0 = time.perf_counter()
+
+    def submit(i):
+        r = requests[i]
+        P = torch.from_numpy(np.ascontiguousarray(r.densities[r.k])).cuda()
+        nbf = P.shape[0]
+        V = torch.empty((nbf, nbf), dtype=torch.float64, device="cuda")
+        EN = torch.empty(2, dtype=torch.float64, device="cuda")
+        t = eng.submit(r.req_id, P, V, EN)
+        inflight[t] = (i, time.perf_counter(), P, V, EN)
+
+    try:
+        while nxt < len(order) or inflight:
+            now = time.perf_counter() - t0
+            while nxt < len(order) and requests[order[nxt]].arrival <= now:
+                i = order[nxt]
+                r = requests[i]
+                r.req_id, _ = eng.add(r)
+                submit(i)
+                nxt += 1
+            if not inflight:
+                wait = requests[order[nxt]].arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.05))
+                continue
+            eng.step()
+            for t in list(inflight):
+                if not eng.poll(t):
+                    continue
+                i, ts, P, V, EN = inflight.pop(t)
+                r = requests[i]
+                te = time.perf_counter()
+                en = EN.cpu().numpy()
+                vv = V.cpu().numpy() if (keep_v is not None and keep_v(i)) else None
+                r.results.append((float(en[0]), float(en[1]), vv))
+                r.int_latency.append(te - ts)
+                n_done_int += 1
+                points_done += r.n_points_nominal
+                r.k += 1
+                if r.k < len(r.densities):
+                    submit(i)
+                else:
+                    r.t_done = te - t0
+                    eng.release(r.req_id)
+                    if log:
+                        log(f"request {i} {r.name} done: {len(r.results)} iterations, "
+                            f"t = {r.t_done:.3f} s")
+        wall = time.perf_counter() - t0
+        st = eng.stats()
+    finally:
+        eng.close()
+    lat = np.array([x for r in requests for x in r.int_latency])
+    req_lat = np.array([r.t_done - r.arrival for r in requests])
+    return {
+        "wall_s": wall,
+        "integrations": n_done_int,
+        "points_per_s": points_done / wall if wall > 0 else 0.0,
+        "integrations_per_s": n_done_int / wall if wall > 0 else 0.0,
+        "latency_p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+        "latency_p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+        "request_latency_p50_s": float(np.percentile(req_lat, 50)) if req_lat.size else None,
+        "request_latency_p99_s": float(np.percentile(req_lat, 99)) if req_lat.size else None,
+        "engine": st,
+    }

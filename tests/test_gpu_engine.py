@@ -1,0 +1,83 @@
+"""Continuous-batching engine through the C ABI: every integration gives the
+same result alone and co-batched with other requests (FP64: 1e-12 relative;
+the only difference is the order of the FP64 atomic adds into V), admission
+under a small device budget, and one request against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import say
+from workloads import cfg_water_cluster, grid_spec_dict
+from workloads.density import perturbed_density
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(n=5, n_iter=3, precision="fp64"):
+    from paper_2007_03143_amd.serving import ServeRequest
+    out = []
+    for i in range(n):
+        nw = 1 + (i % 3)
+        f = "lda" if i % 2 == 0 else "pbe"
+        w = cfg_water_cluster(nw, functional=f, n_rad=40, n_ang=110, seed=100 + i,
+                              n_occ=5 * nw)
+        dens = [perturbed_density(w.P, 1e-3, seed=1000 * i + k) for k in range(n_iter)]
+        out.append(ServeRequest(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w), f, dens,
+                                arrival=0.004 * i, precision=precision, name=w.name,
+                                n_points_nominal=w.n_points_nominal))
+    return out
+
+
+def _alone(r):
+    import torch
+    from paper_2007_03143_amd import XcContext
+    ctx = XcContext(r.coords, r.mk_alpha, r.basis, r.grid)
+    res = []
+    try:
+        for P in r.densities:
+            V, EN = ctx.integrate(torch.from_numpy(P).cuda(), r.functional, r.precision)
+            torch.cuda.synchronize()
+            en = EN.cpu().numpy()
+            res.append((float(en[0]), float(en[1]), V.cpu().numpy()))
+    finally:
+        ctx.close()
+    return res
+
+
+@pytest.mark.parametrize("wave_bytes,budget", [(4 << 20, 0), (64 << 20, 0),
+                                               (4 << 20, 96 << 20)])
+def test_engine_alone_equals_mixed(wave_bytes, budget):
+    from paper_2007_03143_amd.serving import serve
+    reqs = _requests()
+    say(f"case engine wave_bytes {wave_bytes} budget {budget}")
+    ref = [_alone(r) for r in reqs]
+    summary = serve(reqs, hbm_budget=budget, wave_bytes=wave_bytes, keep_v=lambda i: True)
+    say(f"  {summary['integrations']} integrations, steps {summary['engine']['steps']}, "
+        f"p50 {summary['latency_p50_ms']:.2f} ms p99 {summary['latency_p99_ms']:.2f} ms")
+    assert summary["integrations"] == sum(len(r.densities) for r in reqs)
+    for r, rr in zip(reqs, ref):
+        assert len(r.results) == len(rr)
+        for (E, N, V), (E0, N0, V0) in zip(r.results, rr):
+            assert abs(E - E0) <= 1e-12 * abs(E0)
+            assert abs(N - N0) <= 1e-12 * abs(N0)
+            assert np.abs(V - V0).max() <= 1e-12 * np.abs(V0).max()
+            assert np.array_equal(V, V.T)
+
+
+def test_engine_mixed_precisions_and_oracle():
+    from paper_2007_03143_amd.serving import serve
+    reqs = _requests(n=4, n_iter=2)
+    reqs[1].precision = "fp32"
+    ref = [_alone(r) for r in reqs]
+    serve(reqs, wave_bytes=8 << 20, keep_v=lambda i: True)
+    for r, rr in zip(reqs, ref):
+        for (E, N, V), (E0, N0, V0) in zip(r.results, rr):
+            assert abs(E - E0) <= 1e-12 * abs(E0)
+            assert np.abs(V - V0).max() <= 1e-12 * np.abs(V0).max()
+    r = reqs[0]
+    Eo, No, Vo = oracle.integrate(r.coords, r.mk_alpha, r.basis, r.densities[1],
+                                  r.functional, r.grid["n_rad"], r.grid["ang"])
+    E, N, V = r.results[1]
+    say(f"  engine vs oracle: dE {E - Eo:.2e} dN {N - No:.2e} dV {np.abs(V - Vo).max():.2e}")
+    assert abs(E - Eo) <= 1e-10 and abs(N - No) <= 1e-10
+    assert np.abs(V - Vo).max() <= 1e-10

@@ -71,6 +71,48 @@ def cpu_baseline(w, functional, stride):
                       f"{dt:.1f} s"}
 
 
+def serving_run(n_req, warm_pts_per_s, seed=5, log_every=0):
+    """The serving stream: n_req requests (1-100 waters, LDA/PBE, 6-12 SCF
+    iterations, 75 x 302 grid) with Poisson arrivals at 0.7 x the rate the
+    warm FP64 throughput could sustain; densities made on the device."""
+    import torch
+    from paper_2007_03143_amd.serving import ServeRequest, DeviceDensities, serve
+    from workloads import grid_spec_dict
+    from workloads.configs import serving_stream
+    import oracle
+    stream = serving_stream(n_req, seed=seed)
+    mean_pts = np.mean([w.n_points_nominal * n for w, n, _ in stream])
+    lam = 0.7 * warm_pts_per_s / mean_pts
+    rng = np.random.default_rng([seed, 99])
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+    arrivals -= arrivals[0]
+    reqs = []
+    for (w, n_iter, dseed), t in zip(stream, arrivals):
+        reqs.append(ServeRequest(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w),
+                                 w.functional, DeviceDensities(w.nbf, w.n_occ, n_iter, dseed),
+                                 arrival=float(t), name=w.name,
+                                 n_points_nominal=w.n_points_nominal))
+    small = [i for i, (w, _, _) in enumerate(stream) if w.natoms <= 12]
+    n_check = max(1, int(round(0.05 * n_req)))
+    check = sorted(rng.choice(small, size=min(n_check, len(small)), replace=False).tolist()) \
+        if small else []
+    summary = serve(reqs, wave_bytes=2 << 30, keep_v=lambda i: i in check)
+    checks = []
+    for i in check:
+        r = reqs[i]
+        P0 = r.densities.host(0)
+        r.densities.release()
+        Eo, No, Vo = oracle.integrate(r.coords, r.mk_alpha, r.basis, P0, r.functional,
+                                      r.grid["n_rad"], r.grid["ang"])
+        E, N, V = r.results[0]
+        checks.append({"request": i, "name": r.name, "dE_xc": E - Eo, "dN_e": N - No,
+                       "max_dV": float(np.abs(V - Vo).max())})
+    summary.update({"requests": n_req, "arrival_rate_per_s": lam,
+                    "mean_points_per_request": mean_pts, "oracle_checks": checks,
+                    "grid": "75x302", "wave_bytes": 2 << 30})
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +124,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-merge", type=int, default=1)
     ap.add_argument("--mixed", default="fp32")
+    ap.add_argument("--serving", type=int, default=40,
+                    help="requests in the serving stream (0: skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -196,6 +240,13 @@ def main():
         "V_symmetric": bool(np.array_equal(V, V.T)),
     }
     ctx.close()
+    del P
+    torch.cuda.empty_cache()
+    if args.serving > 0:
+        log(f"serving stream of {args.serving} requests")
+        out["serving"] = serving_run(args.serving, n_nom / (ms_warm * 1e-3))
+        log(f"serving: p50 {out['serving']['latency_p50_ms']:.1f} ms "
+            f"p99 {out['serving']['latency_p99_ms']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(w, functional, args.cpu_stride)

@@ -115,7 +115,8 @@ void release_build_temporaries(xc_context* c) {
 
 size_t device_bytes(const xc_context* c) {
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->raw_x, &c->raw_y,
+                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn,
+                            &c->raw_x, &c->raw_y,
                             &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                             &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
                             &c->blk_off, &c->atom_count, &c->cells_a, &c->cells_b,
@@ -200,7 +201,8 @@ static int check_func_prec(int functional, int precision) {
 
 static void release_all(xc_context* c) {
     DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->raw_x, &c->raw_y,
+                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn,
+                      &c->raw_x, &c->raw_y,
                       &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                       &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
                       &c->blk_off, &c->atom_count, &c->cells_a, &c->cells_b,
@@ -254,11 +256,11 @@ static int plan_waves(xc_context* c) {
         const int ngp = (ng + kColPad - 1) / kColPad * kColPad;
         const int nmt = (nb + kTile - 1) / kTile;
         const size_t slab = (size_t)nbp * ngp;
-        const size_t bytes = 8 * (4 * slab + (size_t)nmt * 4 * ngp);
+        const size_t bytes = 8 * (kSlabs * slab + (size_t)nmt * 4 * ngp);
         if (cur.count > 0 && used + bytes > budget) close_wave();
         WaveBatch w{};
         w.phi_off = (long long)(used / 8);
-        w.part_off = (long long)(used / 8 + 4 * slab);
+        w.part_off = (long long)(used / 8 + kSlabs * slab);
         w.pt_off = b.begin;
         w.shell_off = c->h_shoff[j];
         w.func_off = c->h_fnoff[j];
@@ -389,6 +391,15 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
         ff += ncart(basis->shell_L[s]);
     }
     c->nbf = ff;
+    std::vector<int> fshell, flmn;
+    for (int s2 = 0; s2 < c->nshells; ++s2) {
+        const int L = basis->shell_L[s2];
+        for (int l = L; l >= 0; --l)
+            for (int m = L - l; m >= 0; --m) {
+                fshell.push_back(s2);
+                flmn.push_back(l | (m << 4) | ((L - l - m) << 8));
+            }
+    }
     c->prim_alpha.assign(basis->prim_alpha, basis->prim_alpha + po);
     c->prim_coef.assign(basis->prim_coef, basis->prim_coef + po);
     c->n_rad = g->n_rad;
@@ -409,6 +420,8 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
     if (rc == XC_OK) rc = dev_reserve(c->d_nnhalf, 8 * (size_t)c->natoms);
     if (rc == XC_OK) rc = upload(c->d_shells, sh.data(), sizeof(ShellDev) * sh.size(), c->stream);
     if (rc == XC_OK) rc = upload(c->d_palpha, c->prim_alpha.data(), 8 * (size_t)po, c->stream);
+    if (rc == XC_OK) rc = upload(c->d_fshell, fshell.data(), sizeof(int) * fshell.size(), c->stream);
+    if (rc == XC_OK) rc = upload(c->d_flmn, flmn.data(), sizeof(int) * flmn.size(), c->stream);
     if (rc == XC_OK) rc = upload(c->d_pcoef, c->prim_coef.data(), 8 * (size_t)po, c->stream);
     if (rc == XC_OK) rc = upload(c->d_ang, c->ang.data(), 8 * c->ang.size(), c->stream);
     if (rc == XC_OK) {
@@ -465,7 +478,7 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
     size_t pers = 0;
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells,
                             &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
-                            &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
+                            &c->d_fshell, &c->d_flmn, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->epart, &c->npart};
     for (const DevBuf* b : bufs) pers += b->cap;

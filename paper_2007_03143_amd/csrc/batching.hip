@@ -67,15 +67,17 @@ __device__ inline int cell_coord(double v, double lo, double ext, int ns) {
     return t < 0 ? 0 : (t >= ns ? ns - 1 : t);
 }
 
-// One workgroup (256 threads) splits one cell. Thread t owns a contiguous
-// chunk of the cell's points; per-thread child counts and a scan over
-// (child, thread) give every point its stable destination.
-__global__ __launch_bounds__(256) void k_split(
+// One workgroup (kSplitThreads threads) splits one cell. Thread t owns a
+// contiguous chunk of the cell's points; per-thread child counts and a scan
+// over (child, thread) give every point its stable destination.
+constexpr int kSplitThreads = 1024;
+
+__global__ __launch_bounds__(kSplitThreads) void k_split(
     const Cell* cells, const double4* atoms, int natoms, double* X, double* Y,
     double* Z, double* W, long long* I, double* TX, double* TY, double* TZ,
     double* TW, long long* TI, int* child_count, long long* child_begin) {
     const Cell c = cells[blockIdx.x];
-    __shared__ int cnt[256][kMaxChild + 1];
+    __shared__ int cnt[kSplitThreads][kMaxChild + 1];
     __shared__ int tot[kMaxChild + 1], base[kMaxChild + 1];
     __shared__ int has_centre;
     const int tid = threadIdx.x;
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(256) void k_split(
     const int nchild = ns * ns * ns;
     const double ex = c.hi[0] - c.lo[0], ey = c.hi[1] - c.lo[1], ez = c.hi[2] - c.lo[2];
     const int n = c.count;
-    const int chunk = (n + 255) / 256;
+    const int chunk = (n + kSplitThreads - 1) / kSplitThreads;
     const int s0 = min(n, tid * chunk), s1 = min(n, s0 + chunk);
     for (int k = 0; k < kMaxChild; ++k) cnt[tid][k] = 0;
     for (int j = s0; j < s1; ++j) {
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void k_split(
     __syncthreads();
     if (tid < nchild) {
         int run = 0;
-        for (int t = 0; t < 256; ++t) {
+        for (int t = 0; t < kSplitThreads; ++t) {
             const int v = cnt[t][tid];
             cnt[t][tid] = run;
             run += v;
@@ -264,7 +266,7 @@ int run_batching(xc_context* c, const std::vector<long long>& atom_kept) {
         XC_TRY(dev_reserve(c->child_begin, sizeof(long long) * nch));
         XC_TRY(dev_reserve(c->cells_b, sizeof(Cell) * nch));
         XC_TRY(dev_reserve(c->batches, sizeof(Cell) * nch));
-        hipLaunchKernelGGL(k_split, dim3(ncur), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL(k_split, dim3(ncur), dim3(kSplitThreads), 0, c->stream,
                            (const Cell*)c->cells_a.p, (const double4*)c->d_atoms.p,
                            c->natoms, (double*)c->px.p, (double*)c->py.p,
                            (double*)c->pz.p, (double*)c->pw.p, (long long*)c->pidx.p,

@@ -63,7 +63,7 @@ namespace xc {
 int build_grid(xc_context* c);
 
 static size_t batch_bytes(const WaveBatch& w) {
-    return 8 * (4 * (size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
+    return 8 * (kSlabs * (size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
 }
 
 // Device bytes an unbuilt context is expected to need while it is built and
@@ -171,7 +171,7 @@ static int engine_step(xc_engine* e, int* launched) {
                 req_slot = sl->second;
             }
             w.phi_off = (long long)(used / 8);
-            w.part_off = (long long)(used / 8 + 4 * (size_t)w.nbp * w.ngp);
+            w.part_off = (long long)(used / 8 + kSlabs * (size_t)w.nbp * w.ngp);
             w.req = req_slot;
             used += bytes;
             const int gt = w.nmt * (w.ngp / kTile);

@@ -113,21 +113,26 @@ __device__ inline double ssf_s(double mu, double a) {
     return 0.5 * (1.0 - g);
 }
 
-__device__ inline double dist_to(const double4& at, double x, double y, double z) {
+__device__ inline double dist2_to(const double4& at, double x, double y, double z) {
     const double dx = x - at.x, dy = y - at.y, dz = z - at.z;
-    return sqrt(dx * dx + dy * dy + dz * dz);
+    return dx * dx + dy * dy + dz * dz;
 }
 
 // Unnormalised cell product P_C(r) = prod_{B != C} s(mu_CB); stops at zero.
+// An atom B with d_B >= d_C (1 + a)/(1 - a) has mu_CB <= -a (because
+// R_CB <= d_B + d_C), so s(mu_CB) = 1 exactly and it is skipped on its
+// squared distance alone.
 __device__ inline double ssf_product(int C, double dC, const double4* atoms,
                                      const double* invR, int natoms, double x,
-                                     double y, double z, double a) {
+                                     double y, double z, double a, double far2) {
     double p = 1.0;
     const double* ir = invR + (size_t)C * natoms;
+    const double lim2 = dC * dC * far2;
     for (int B = 0; B < natoms; ++B) {
         if (B == C) continue;
-        const double dB = dist_to(atoms[B], x, y, z);
-        p *= ssf_s((dC - dB) * ir[B], a);
+        const double d2 = dist2_to(atoms[B], x, y, z);
+        if (d2 >= lim2) continue;
+        p *= ssf_s((dC - sqrt(d2)) * ir[B], a);
         if (p == 0.0) break;
     }
     return p;
@@ -136,42 +141,61 @@ __device__ inline double ssf_product(int C, double dC, const double4* atoms,
 // w_i <- w_i * P_parent / sum_C P_C. Exact reductions of the work:
 //  * |r - R_A| < (1-a)/2 min_B R_AB: the parent owns the point (p = 1);
 //  * an atom C with (d_C - d_min) / R_{C,nearest} >= a has s(mu_{C,nearest}) = 0,
-//    hence P_C = 0, and is skipped.
-__global__ void k_ssf(long long n, int npa, const int* gatoms, const double4* atoms,
-                      const double* invR, const double* nnhalf, int natoms,
-                      double a, const double* X, const double* Y, const double* Z,
-                      double* W) {
+//    hence P_C = 0, and is skipped;
+//  * inside a product, atoms far beyond d_C contribute factors of exactly 1.
+// Atom centres are staged in LDS and read by every lane of a wave together.
+constexpr int kSsfLdsAtoms = 2048;
+
+__global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* gatoms,
+                                             const double4* atoms_g, const double* invR,
+                                             const double* nnhalf, int natoms, double a,
+                                             const double* X, const double* Y,
+                                             const double* Z, double* W) {
+    __shared__ double4 sat[kSsfLdsAtoms];
+    const bool in_lds = natoms <= kSsfLdsAtoms;
+    if (in_lds)
+        for (int k = threadIdx.x; k < natoms; k += blockDim.x) sat[k] = atoms_g[k];
+    __syncthreads();
+    const double4* atoms = in_lds ? sat : atoms_g;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double w = W[i];
     if (w == 0.0 || natoms == 1) return;
     const int A = gatoms[(int)(i / npa)];
     const double x = X[i], y = Y[i], z = Z[i];
-    const double dA = dist_to(atoms[A], x, y, z);
+    const double dA = sqrt(dist2_to(atoms[A], x, y, z));
     if (dA < nnhalf[A]) return;
-    double dmin = INFINITY;
+    const double far = (1.0 + a) / (1.0 - a) * (1.0 + 1e-12);
+    const double far2 = far * far;
+    double dmin2 = INFINITY;
     int bmin = 0;
     for (int B = 0; B < natoms; ++B) {
-        const double d = dist_to(atoms[B], x, y, z);
-        if (d < dmin) {
-            dmin = d;
+        const double d2 = dist2_to(atoms[B], x, y, z);
+        if (d2 < dmin2) {
+            dmin2 = d2;
             bmin = B;
         }
     }
-    const double PA = ssf_product(A, dA, atoms, invR, natoms, x, y, z, a);
+    const double dmin = sqrt(dmin2);
+    const double PA = ssf_product(A, dA, atoms, invR, natoms, x, y, z, a, far2);
     if (PA == 0.0) {
         W[i] = 0.0;
         return;
     }
+    // candidates C need d_C < d_min + a R_{C,nearest} <= d_min + a (d_C + d_min)
+    const double cand = dmin * (1.0 + a) / (1.0 - a) * (1.0 + 1e-12);
+    const double cand2 = cand * cand;
     double sum = 0.0;
     for (int C = 0; C < natoms; ++C) {
         if (C == A) {
             sum += PA;
             continue;
         }
-        const double dC = dist_to(atoms[C], x, y, z);
+        const double dC2 = dist2_to(atoms[C], x, y, z);
+        if (C != bmin && dC2 >= cand2) continue;
+        const double dC = sqrt(dC2);
         if (C != bmin && (dC - dmin) * invR[(size_t)C * natoms + bmin] >= a) continue;
-        sum += ssf_product(C, dC, atoms, invR, natoms, x, y, z, a);
+        sum += ssf_product(C, dC, atoms, invR, natoms, x, y, z, a, far2);
     }
     W[i] = w * (PA / sum);
 }

@@ -3,14 +3,16 @@
 // eq. z_mat; Sec. 2.3.2 Alg. 4).
 //
 // For every batch j of a wave, in four launches over all its batches:
-//  1. collocation  Phi^j (n_b x n_g) and, for the GGA, grad Phi^j, written in
-//     compressed form over the screened functions;
-//  2. X = P^j Phi^j on FP64 MFMA with P^j gathered straight from the full
-//     P (never packed), and rho, grad rho reduced from X in the epilogue
+//  1. collocation Phi^j (n_b x n_g), written in compressed form over the
+//     screened functions (only Phi is stored; gradients are re-evaluated
+//     from the shell data wherever they are needed, which costs far less
+//     than moving three more n_b x n_g slabs through HBM);
+//  2. X = P^j Phi^j on MFMA with P^j gathered straight from the full P
+//     (never packed), and rho, grad rho reduced from X in the epilogue
 //     (X is never stored);
 //  3. the functional per point, the batch's E_xc and N_e partials, and
 //     Z^j = (1/2) w v_rho Phi + 2 w v_sigma grad rho . grad Phi;
-//  4. V^j = Z Phi^T + Phi Z^T on FP64 MFMA over lower-triangle tiles only,
+//  4. V^j = Z Phi^T + Phi Z^T on MFMA over lower-triangle tiles only,
 //     added into the lower triangle of the full V with FP64 atomics.
 // Then V is mirrored and E_xc, N_e are summed in a fixed order.
 #include <cmath>
@@ -49,14 +51,76 @@ template <> struct Mfma<float> {
 };
 
 // ------------------------------------------------------------ collocation --
-// Values (and gradients) of the (L+1)(L+2)/2 Cartesian functions of one
-// shell at one point, written down the rows starting at out (row stride ngp;
-// gradients at +slab, +2 slab, +3 slab).
-template <int L, bool GGA, typename T>
-__device__ inline void colloc_shell(T dx, T dy, T dz, T rad, T drad, bool live, T* out,
-                                    int ngp, size_t slab) {
-    T xp[L + 1], yp[L + 1], zp[L + 1];
-    xp[0] = yp[0] = zp[0] = T(1);
+// Radial part of a shell at squared distance r2: rad = sum_xi d e^{-alpha r2}
+// and drad = -2 sum_xi alpha d e^{-alpha r2} (d rad / d r2 times 2), zero
+// outside the cutoff sphere.
+__device__ inline void shell_radial(const ShellDev& sh, const double* palpha,
+                                    const double* pcoef, double r2, double& rad,
+                                    double& drad) {
+    rad = 0.0;
+    drad = 0.0;
+    if (!(r2 <= sh.rcut2)) return;
+    for (int p = 0; p < sh.nprim; ++p) {
+        const double a = palpha[sh.prim_off + p];
+        const double de = pcoef[sh.prim_off + p] * exp(-a * r2);
+        rad += de;
+        drad -= 2.0 * a * de;
+    }
+}
+
+// Squared distance with the same rounding in every kernel (no contraction),
+// so the cutoff test gives the same answer wherever it is evaluated.
+__device__ inline double dist2_nc(double x, double y, double z, const ShellDev& sh,
+                                  double& dx, double& dy, double& dz) {
+#pragma clang fp contract(off)
+    dx = x - sh.x;
+    dy = y - sh.y;
+    dz = z - sh.z;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ inline double ipow3(double x, int n) {
+    return n == 0 ? 1.0 : (n == 1 ? x : (n == 2 ? x * x : x * x * x));
+}
+
+// Value and gradient of x^l y^m z^n rad(r^2) (eq. gau_cart).
+__device__ inline void cart_eval(int l, int m, int n, double dx, double dy, double dz,
+                                 double rad, double drad, double& v, double& gx,
+                                 double& gy, double& gz) {
+    const double xl = ipow3(dx, l), ym = ipow3(dy, m), zn = ipow3(dz, n);
+    const double ang = xl * ym * zn;
+    v = ang * rad;
+    const double ad = ang * drad;
+    gx = (l ? l * ipow3(dx, l - 1) * ym * zn : 0.0) * rad + ad * dx;
+    gy = (m ? m * xl * ipow3(dy, m - 1) * zn : 0.0) * rad + ad * dy;
+    gz = (n ? n * xl * ym * ipow3(dz, n - 1) : 0.0) * rad + ad * dz;
+}
+
+// Z entries of the (L+1)(L+2)/2 functions of one shell at one point:
+// z = a phi + b . grad phi, written down the rows starting at out.
+template <int L, typename T>
+__device__ inline void z_shell(double dx, double dy, double dz, double rad, double drad,
+                               double a, double bx, double by, double bz, T* out,
+                               int ngp) {
+    int c = 0;
+#pragma unroll
+    for (int l = L; l >= 0; --l) {
+#pragma unroll
+        for (int m = L - l; m >= 0; --m) {
+            const int n = L - l - m;
+            double v, gx, gy, gz;
+            cart_eval(l, m, n, dx, dy, dz, rad, drad, v, gx, gy, gz);
+            out[(size_t)c * ngp] = T(a * v + bx * gx + by * gy + bz * gz);
+            ++c;
+        }
+    }
+}
+
+template <int L, typename T>
+__device__ inline void phi_shell(double dx, double dy, double dz, double rad, T* out,
+                                 int ngp) {
+    double xp[L + 1], yp[L + 1], zp[L + 1];
+    xp[0] = yp[0] = zp[0] = 1.0;
 #pragma unroll
     for (int k = 1; k <= L; ++k) {
         xp[k] = xp[k - 1] * dx;
@@ -68,28 +132,7 @@ __device__ inline void colloc_shell(T dx, T dy, T dz, T rad, T drad, bool live, 
     for (int l = L; l >= 0; --l) {
 #pragma unroll
         for (int m = L - l; m >= 0; --m) {
-            const int n = L - l - m;
-            T* o = out + (size_t)c * ngp;
-            if (!live) {
-                o[0] = T(0);
-                if (GGA) {
-                    o[slab] = T(0);
-                    o[2 * slab] = T(0);
-                    o[3 * slab] = T(0);
-                }
-            } else {
-                const T ang = xp[l] * yp[m] * zp[n];
-                o[0] = ang * rad;
-                if (GGA) {
-                    const T ad = ang * drad;
-                    const T gx = (l ? T(l) * xp[l - 1] * yp[m] * zp[n] : T(0));
-                    const T gy = (m ? T(m) * xp[l] * yp[m - 1] * zp[n] : T(0));
-                    const T gz = (n ? T(n) * xp[l] * yp[m] * zp[n - 1] : T(0));
-                    o[slab] = gx * rad + ad * dx;
-                    o[2 * slab] = gy * rad + ad * dy;
-                    o[3 * slab] = gz * rad + ad * dz;
-                }
-            }
+            out[(size_t)c * ngp] = T(xp[l] * yp[m] * zp[L - l - m] * rad);
             ++c;
         }
     }
@@ -97,74 +140,42 @@ __device__ inline void colloc_shell(T dx, T dy, T dz, T rad, T drad, bool live, 
 
 // One workgroup per batch; wave w evaluates shells w, w+4, ... of the
 // batch's screened list, one lane per point, so a wave never diverges on
-// the contraction length. Points of the batch are staged in LDS.
-template <bool GGA, typename T>
+// the contraction length. Points of the batch are staged in LDS. Values are
+// formed in FP64 in every mode and rounded once on store.
+template <typename T>
 __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb,
                                                 const ReqDev* __restrict__ reqs,
                                                 char* __restrict__ scratch) {
     const WaveBatch B = wb[blockIdx.x];
     const ReqDev R = reqs[B.req];
-    const ShellDev* __restrict__ shells = R.shells;
-    const double* __restrict__ palpha = R.palpha;
-    const double* __restrict__ pcoef = R.pcoef;
-    const int* __restrict__ shell_list = R.shell_list;
-    const int* __restrict__ shell_loff = R.shell_loff;
-    const double* __restrict__ X = R.px;
-    const double* __restrict__ Y = R.py;
-    const double* __restrict__ Z = R.pz;
     __shared__ double sx[kMaxBatch], sy[kMaxBatch], sz[kMaxBatch];
     for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
         const bool v = i < B.ng;
-        sx[i] = v ? X[B.pt_off + i] : 0.0;
-        sy[i] = v ? Y[B.pt_off + i] : 0.0;
-        sz[i] = v ? Z[B.pt_off + i] : 0.0;
+        sx[i] = v ? R.px[B.pt_off + i] : 0.0;
+        sy[i] = v ? R.py[B.pt_off + i] : 0.0;
+        sz[i] = v ? R.pz[B.pt_off + i] : 0.0;
     }
     __syncthreads();
     T* Phi = (T*)(scratch + 8 * B.phi_off);
-    const size_t slab = (size_t)B.nbp * B.ngp;
     // zero the padding rows n_b .. n_bp - 1
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
-    for (long long k = threadIdx.x; k < npad; k += blockDim.x) {
-        const size_t off = (size_t)B.nb * B.ngp + k;
-        Phi[off] = T(0);
-        if (GGA) {
-            Phi[slab + off] = T(0);
-            Phi[2 * slab + off] = T(0);
-            Phi[3 * slab + off] = T(0);
-        }
-    }
+    for (long long k = threadIdx.x; k < npad; k += blockDim.x) Phi[(size_t)B.nb * B.ngp + k] = T(0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int sl = wave; sl < B.nshell; sl += 4) {
-        const int s = shell_list[B.shell_off + sl];
-        const int loff = shell_loff[B.shell_off + sl];
-        const ShellDev sh = shells[s];
+        const int s = R.shell_list[B.shell_off + sl];
+        const int loff = R.shell_loff[B.shell_off + sl];
+        const ShellDev sh = R.shells[s];
         for (int i = lane; i < B.ngp; i += 64) {
-            double dx, dy, dz, r2;
-            {
-#pragma clang fp contract(off)
-                dx = sx[i] - sh.x;
-                dy = sy[i] - sh.y;
-                dz = sz[i] - sh.z;
-                r2 = dx * dx + dy * dy + dz * dz;
-            }
-            const bool live = (i < B.ng) && (r2 <= sh.rcut2);
-            T rad = T(0), drad = T(0);
-            if (live) {
-                const T tr2 = T(r2);
-                for (int p = 0; p < sh.nprim; ++p) {
-                    const T a = T(palpha[sh.prim_off + p]);
-                    const T de = T(pcoef[sh.prim_off + p]) * exp(-a * tr2);
-                    rad += de;
-                    drad -= T(2) * a * de;
-                }
-            }
+            double dx, dy, dz, rad, drad;
+            const double r2 = dist2_nc(sx[i], sy[i], sz[i], sh, dx, dy, dz);
+            if (i < B.ng) shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
+            else rad = drad = 0.0;
             T* out = Phi + (size_t)loff * B.ngp + i;
-            const T tx = T(dx), ty = T(dy), tz = T(dz);
             switch (sh.L) {
-                case 0: colloc_shell<0, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
-                case 1: colloc_shell<1, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
-                case 2: colloc_shell<2, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
-                default: colloc_shell<3, GGA, T>(tx, ty, tz, rad, drad, live, out, B.ngp, slab); break;
+                case 0: phi_shell<0, T>(dx, dy, dz, rad, out, B.ngp); break;
+                case 1: phi_shell<1, T>(dx, dy, dz, rad, out, B.ngp); break;
+                case 2: phi_shell<2, T>(dx, dy, dz, rad, out, B.ngp); break;
+                default: phi_shell<3, T>(dx, dy, dz, rad, out, B.ngp); break;
             }
         }
     }
@@ -172,9 +183,11 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
 
 // ------------------------------------------------------- density (GEMM) ----
 // Tile of 64 functions x 64 points of X = P^j Phi^j; 4 waves, each a 32 x 32
-// block of 2 x 2 MFMA 16x16x4 FP64 tiles. A operand rows are gathered from
-// the full P through the batch's function list. The epilogue reduces
-// Phi*X (and grad Phi * X) over the tile's rows into per-row-tile partials
+// block of 2 x 2 MFMA 16x16x4 tiles. A operand rows are gathered from the
+// full P through the batch's function list. The epilogue spills X to LDS;
+// then each thread takes one point and 16 consecutive functions (mostly of
+// one or two shells), re-evaluates phi (and grad phi) from the shell data in
+// FP64 and reduces phi*X (grad phi * X) into per-row-tile partials
 // part[mt][q][point], q = rho, dx, dy, dz.
 template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_gemm_rho(
@@ -192,18 +205,28 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int ntn = B.ngp / kTile;
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
-    const size_t slab = (size_t)B.nbp * B.ngp;
     const T* Phi = (const T*)(scratch + 8 * B.phi_off);
     const int* fl = func_list + B.func_off;
 
-    __shared__ T As[2][kTile][17];
-    __shared__ T Bs[2][16][kTile + 1];
-    __shared__ int frow[kTile];
-    __shared__ double red[4][kTile];
+    // operand tiles during the main loop, the X tile in the epilogue
+    constexpr int kABytes = 2 * kTile * 17 * (int)sizeof(T);
+    constexpr int kBBytes = 2 * 16 * (kTile + 1) * (int)sizeof(T);
+    constexpr int kXBytes = kTile * (kTile + 1) * 8;
+    constexpr int kLds = (kABytes + kBBytes > kXBytes) ? kABytes + kBBytes : kXBytes;
+    __shared__ __attribute__((aligned(16))) char lds[kLds];
+    T (*As)[kTile][17] = reinterpret_cast<T (*)[kTile][17]>(lds);
+    T (*Bs)[16][kTile + 1] = reinterpret_cast<T (*)[16][kTile + 1]>(lds + kABytes);
+    double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
+    __shared__ int frow[kTile], fsh[kTile], flmn[kTile];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    if (tid < kTile) frow[tid] = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
+    if (tid < kTile) {
+        const int f = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
+        frow[tid] = f;
+        fsh[tid] = f >= 0 ? R.func_shell[f] : 0;
+        flmn[tid] = f >= 0 ? R.func_lmn[f] : 0;
+    }
     __syncthreads();
 
     const int ar = tid >> 2, ac = (tid & 3) * 4;
@@ -272,60 +295,74 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         __syncthreads();
     }
 
-    constexpr int NQ = GGA ? 4 : 1;
-    double q[NQ][2];
+    // spill X (the loop ended on a barrier, so the operand tiles are free)
 #pragma unroll
-    for (int qq = 0; qq < NQ; ++qq) q[qq][0] = q[qq][1] = 0.0;
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
+        for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = m0 + wm * 32 + mb * 16 + M::acc_row(r, lane);
-            if (row < B.nb) {
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    const int col = n0 + wn * 32 + nb * 16 + (lane & 15);
-                    const T x = acc[mb][nb][r];
-                    const size_t off = (size_t)row * B.ngp + col;
-                    q[0][nb] += double(Phi[off] * x);
-                    if (GGA) {
-                        q[1 % NQ][nb] += double(Phi[slab + off] * x);
-                        q[2 % NQ][nb] += double(Phi[2 * slab + off] * x);
-                        q[3 % NQ][nb] += double(Phi[3 * slab + off] * x);
-                    }
-                }
+            for (int r = 0; r < 4; ++r)
+                Xs[wm * 32 + mb * 16 + M::acc_row(r, lane)][wn * 32 + nb * 16 + (lane & 15)] =
+                    double(acc[mb][nb][r]);
+    __syncthreads();
+
+    const int c = tid & 63, g = tid >> 6;
+    const int col = n0 + c;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    if (col < B.ng) {
+        const double x = R.px[B.pt_off + col], y = R.py[B.pt_off + col],
+                     z = R.pz[B.pt_off + col];
+        int prev = -1;
+        double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
+        for (int rr = 0; rr < 16; ++rr) {
+            const int rl = g * 16 + rr;
+            if (m0 + rl >= B.nb) break;
+            const int sidx = fsh[rl];
+            if (sidx != prev) {
+                const ShellDev sh = R.shells[sidx];
+                const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
+                shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
+                prev = sidx;
+            }
+            const int lmn = flmn[rl];
+            const double xv = Xs[rl][c];
+            if (GGA) {
+                double v, gx, gy, gz;
+                cart_eval(lmn & 15, (lmn >> 4) & 15, lmn >> 8, dx, dy, dz, rad, drad, v, gx,
+                          gy, gz);
+                q0 += v * xv;
+                q1 += gx * xv;
+                q2 += gy * xv;
+                q3 += gz * xv;
+            } else {
+                q0 += ipow3(dx, lmn & 15) * ipow3(dy, (lmn >> 4) & 15) *
+                      ipow3(dz, lmn >> 8) * rad * xv;
             }
         }
-    }
-#pragma unroll
-    for (int qq = 0; qq < NQ; ++qq)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            double v = q[qq][nb];
-            v += __shfl_xor(v, 16, 64);
-            v += __shfl_xor(v, 32, 64);
-            q[qq][nb] = v;
-        }
-    if (wm == 1 && lane < 16) {
-#pragma unroll
-        for (int qq = 0; qq < NQ; ++qq)
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) red[qq][wn * 32 + nb * 16 + lane] = q[qq][nb];
     }
     __syncthreads();
-    if (wm == 0 && lane < 16) {
+    double* red = &Xs[0][0];
+    red[(g * 4 + 0) * kTile + c] = q0;
+    red[(g * 4 + 1) * kTile + c] = q1;
+    red[(g * 4 + 2) * kTile + c] = q2;
+    red[(g * 4 + 3) * kTile + c] = q3;
+    __syncthreads();
+    if (g == 0) {
         double* part = (double*)(scratch + 8 * B.part_off);
+        constexpr int NQ = GGA ? 4 : 1;
 #pragma unroll
-        for (int qq = 0; qq < NQ; ++qq)
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const int ct = wn * 32 + nb * 16 + lane;
-                part[(size_t)(mt * 4 + qq) * B.ngp + n0 + ct] = q[qq][nb] + red[qq][ct];
-            }
+        for (int qq = 0; qq < NQ; ++qq) {
+            const double v = red[(0 * 4 + qq) * kTile + c] + red[(1 * 4 + qq) * kTile + c] +
+                             red[(2 * 4 + qq) * kTile + c] + red[(3 * 4 + qq) * kTile + c];
+            part[(size_t)(mt * 4 + qq) * B.ngp + n0 + c] = v;
+        }
     }
 }
 
 // ------------------------------------------------- functional + Z matrix --
+// One workgroup per batch: rho, grad rho from the partials, the functional
+// per point, the batch's E_xc and N_e partials, then Z^j (eq. z_mat)
+// re-evaluated shell by shell from the shell data and stored in slab 1.
 template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb,
                                                 const ReqDev* __restrict__ reqs,
@@ -334,8 +371,6 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
     const ReqDev& R = reqs[B.req];
     const double* __restrict__ W = R.pw;
     const double rho_thresh = R.rho_thresh;
-    double* __restrict__ epart = R.epart;
-    double* __restrict__ npart = R.npart;
     __shared__ double sa[kMaxBatch], sbx[kMaxBatch], sby[kMaxBatch], sbz[kMaxBatch];
     __shared__ double red[256];
     const double* part = (const double*)(scratch + 8 * B.part_off);
@@ -378,33 +413,39 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
             }
         }
         sa[i] = a;
-        if (GGA) {
-            sbx[i] = bx;
-            sby[i] = by;
-            sbz[i] = bz;
-        }
+        sbx[i] = bx;
+        sby[i] = by;
+        sbz[i] = bz;
     }
     const double es = block_sum_256(eacc, red);
     const double ns = block_sum_256(nacc, red);
     if (threadIdx.x == 0) {
-        epart[B.batch] = es;
-        npart[B.batch] = ns;
+        R.epart[B.batch] = es;
+        R.npart[B.batch] = ns;
     }
-    // Z overwrites slab 1 (the x-gradient for the GGA, which is read first);
-    // formed in FP64 and stored in the storage type
-    T* Phi = (T*)(scratch + 8 * B.phi_off);
-    const size_t slab = (size_t)B.nbp * B.ngp;
-    T* Zm = Phi + slab;
+    T* Zm = (T*)(scratch + 8 * B.phi_off) + (size_t)B.nbp * B.ngp;
+    const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
+    for (long long k = threadIdx.x; k < npad; k += blockDim.x) Zm[(size_t)B.nb * B.ngp + k] = T(0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int row = wave; row < B.nbp; row += 4) {
-        const size_t ro = (size_t)row * B.ngp;
+    for (int sl = wave; sl < B.nshell; sl += 4) {
+        const int sidx = R.shell_list[B.shell_off + sl];
+        const int loff = R.shell_loff[B.shell_off + sl];
+        const ShellDev sh = R.shells[sidx];
         for (int i = lane; i < B.ngp; i += 64) {
-            const size_t off = ro + i;
-            double z = sa[i] * double(Phi[off]);
-            if (GGA)
-                z += sbx[i] * double(Zm[off]) + sby[i] * double(Phi[2 * slab + off]) +
-                     sbz[i] * double(Phi[3 * slab + off]);
-            Zm[off] = T(z);
+            double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
+            if (i < B.ng) {
+                const double r2 = dist2_nc(R.px[B.pt_off + i], R.py[B.pt_off + i],
+                                           R.pz[B.pt_off + i], sh, dx, dy, dz);
+                shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
+            }
+            T* out = Zm + (size_t)loff * B.ngp + i;
+            const double a = sa[i], bx = sbx[i], by = sby[i], bz = sbz[i];
+            switch (sh.L) {
+                case 0: z_shell<0, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+                case 1: z_shell<1, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+                case 2: z_shell<2, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+                default: z_shell<3, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+            }
         }
     }
 }
@@ -581,7 +622,7 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                          int syr_tiles, const ReqDev* reqs, char* scr) {
     {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
-        hipLaunchKernelGGL((k_colloc<GGA, T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        hipLaunchKernelGGL((k_colloc<T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (gemm_tiles > 0) {
@@ -657,6 +698,8 @@ ReqDev make_req(const xc_context* c, const double* dP, double* dV) {
     r.V = dV;
     r.epart = (double*)c->epart.p;
     r.npart = (double*)c->npart.p;
+    r.func_shell = (const int*)c->d_fshell.p;
+    r.func_lmn = (const int*)c->d_flmn.p;
     r.rho_thresh = c->rho_thresh;
     r.nbf = c->nbf;
     return r;

@@ -58,6 +58,10 @@ struct Cell {
     double hi[3];
 };
 
+// Per-batch wave scratch: slab 0 = Phi, slab 1 = Z (n_bp x n_gp each, FP64
+// size whatever the storage type), then the rho / grad rho partials.
+constexpr int kSlabs = 2;
+
 // One batch as the integration kernels of a wave read it.
 struct WaveBatch {
     long long phi_off;  // offset (doubles) of slab 0 of this batch in the wave scratch
@@ -84,6 +88,8 @@ struct ReqDev {
     const int* shell_list;
     const int* shell_loff;
     const int* func_list;
+    const int* func_shell;   // global shell of every global function
+    const int* func_lmn;     // its Cartesian exponents, l | m << 4 | n << 8
     const double* px;
     const double* py;
     const double* pz;
@@ -146,6 +152,7 @@ struct xc_context {
 
     // device inputs
     xc::DevBuf d_atoms, d_invR, d_nnhalf, d_shells, d_palpha, d_pcoef, d_ang, d_gatoms;
+    xc::DevBuf d_fshell, d_flmn;
 
     // grid and batches
     bool built = false;

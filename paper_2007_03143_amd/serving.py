@@ -26,7 +26,7 @@ class ServeRequest:
     basis: object
     grid: dict
     functional: str
-    densities: list            # host (nbf, nbf) arrays, one per SCF iteration
+    densities: object          # list of host (nbf, nbf) arrays, or a DeviceDensities
     arrival: float = 0.0       # seconds after the start of the stream
     precision: str = "fp64"
     name: str = ""
@@ -37,6 +37,43 @@ class ServeRequest:
     results: list = field(default_factory=list)    # (E, N, V or None)
     int_latency: list = field(default_factory=list)
     t_done: float = 0.0
+
+
+class DeviceDensities:
+    """Seeded SCF-like densities made on the device: P_0 = 2 C C^T with C
+    (nbf x n_occ) standard normal / sqrt(nbf), P_k = P_0 + delta_k with
+    delta_k symmetric, standard normal, scaled to Frobenius norm `norm`."""
+
+    def __init__(self, nbf, n_occ, n_iter, seed, norm=1e-3):
+        self.nbf, self.n_occ, self.n_iter, self.seed, self.norm = nbf, n_occ, n_iter, seed, norm
+        self._p0 = None
+
+    def __len__(self):
+        return self.n_iter
+
+    def _gen(self, salt):
+        import torch
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(self.seed) * 1000003 + salt)
+        return g
+
+    def device(self, k):
+        import torch
+        if self._p0 is None:
+            C = torch.randn(self.nbf, self.n_occ, generator=self._gen(0), device="cuda",
+                            dtype=torch.float64) / self.nbf ** 0.5
+            self._p0 = 2.0 * (C @ C.T)
+        d = torch.randn(self.nbf, self.nbf, generator=self._gen(k + 1), device="cuda",
+                        dtype=torch.float64)
+        d = 0.5 * (d + d.T)
+        d *= self.norm / torch.linalg.norm(d)
+        return (self._p0 + d).contiguous()
+
+    def host(self, k):
+        return self.device(k).cpu().numpy()
+
+    def release(self):
+        self._p0 = None
 
 
 class XcEngine:
@@ -89,7 +126,10 @@ def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None):
 
     def submit(i):
         r = requests[i]
-        P = torch.from_numpy(np.ascontiguousarray(r.densities[r.k])).cuda()
+        if isinstance(r.densities, DeviceDensities):
+            P = r.densities.device(r.k)
+        else:
+            P = torch.from_numpy(np.ascontiguousarray(r.densities[r.k])).cuda()
         nbf = P.shape[0]
         V = torch.empty((nbf, nbf), dtype=torch.float64, device="cuda")
         EN = torch.empty(2, dtype=torch.float64, device="cuda")
@@ -129,6 +169,8 @@ def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None):
                 else:
                     r.t_done = te - t0
                     eng.release(r.req_id)
+                    if isinstance(r.densities, DeviceDensities):
+                        r.densities.release()
                     if log:
                         log(f"request {i} {r.name} done: {len(r.results)} iterations, "
                             f"t = {r.t_done:.3f} s")

@@ -120,3 +120,25 @@ def cfg_serving_request(index, seed=5, n_rad=75, n_ang=302):
     dens = [perturbed_density(w.P, 1e-3, seed=seed * 7919 + index * 31 + k)
             for k in range(n_iter)]
     return w, dens
+
+
+def serving_stream(n_requests, seed=5, n_rad=75, n_ang=302, max_waters=100):
+    """Request mix of the serving stream: water clusters of 1..max_waters
+    waters (log-uniform), LDA or PBE (50/50), 6-12 SCF iterations each.
+    Returns (workload, n_iter, density_seed) per request; densities are made
+    on the device by the serving loop from density_seed."""
+    out = []
+    ang = lebedev_table(n_ang)
+    for i in range(n_requests):
+        rng = np.random.default_rng([seed, i])
+        n_w = int(np.clip(np.round(np.exp(rng.uniform(0.0, np.log(max_waters)))), 1,
+                          max_waters))
+        func = "lda" if rng.uniform() < 0.5 else "pbe"
+        n_iter = int(rng.integers(6, 13))
+        box = 25.0 * (n_w / 64.0) ** (1.0 / 3.0)
+        mol = water_cluster(n_w, box=max(box, 5.0), seed=seed * 100003 + i)
+        basis = make_basis(mol.Z, seed=2007)
+        w = Workload(f"req{i}_water{n_w}", mol, basis, None, 5 * n_w, n_rad, n_ang,
+                     func, ang=ang)
+        out.append((w, n_iter, seed * 7919 + i))
+    return out

@@ -100,6 +100,14 @@ class XcError(RuntimeError):
 
 
 def _load():
+    # PyTorch-ROCm carries its own HIP runtime (same soname as the system
+    # one). Loading torch first makes this library bind to that runtime, so
+    # the process holds one HIP runtime whichever module a caller imports
+    # first; two runtimes in one process do not see the same devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "paper_2007_03143_amd/build.py (no CPU fallback exists)")

@@ -115,7 +115,7 @@ void release_build_temporaries(xc_context* c) {
 
 size_t device_bytes(const xc_context* c) {
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn,
+                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn, &c->d_nbr_idx, &c->d_nbr_R,
                             &c->raw_x, &c->raw_y,
                             &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                             &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
@@ -157,6 +157,14 @@ static int validate_inputs(const xc_molecule* mol, const xc_basis* basis,
         if (!(mol->mk_alpha[a] > 0.0) || !finite(mol->mk_alpha[a]))
             return fail(XC_ERR_INVALID_ARG, "Mura-Knowles alpha must be positive");
     }
+    for (int a = 0; a < mol->natoms; ++a)
+        for (int b = 0; b < a; ++b) {
+            const double dx = mol->xyz[3 * a] - mol->xyz[3 * b];
+            const double dy = mol->xyz[3 * a + 1] - mol->xyz[3 * b + 1];
+            const double dz = mol->xyz[3 * a + 2] - mol->xyz[3 * b + 2];
+            if (dx * dx + dy * dy + dz * dz < 1e-16)
+                return fail(XC_ERR_INVALID_ARG, "two atoms at the same position");
+        }
     if (basis->nshells < 1 || !basis->shell_atom || !basis->shell_L || !basis->shell_nprim ||
         !basis->prim_alpha || !basis->prim_coef)
         return fail(XC_ERR_INVALID_ARG, "basis needs nshells >= 1 and all arrays");
@@ -201,7 +209,7 @@ static int check_func_prec(int functional, int precision) {
 
 static void release_all(xc_context* c) {
     DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn,
+                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn, &c->d_nbr_idx, &c->d_nbr_R,
                       &c->raw_x, &c->raw_y,
                       &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                       &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
@@ -418,6 +426,10 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
     if (rc == XC_OK) rc = upload(c->d_atoms, c->atoms4.data(), 8 * c->atoms4.size(), c->stream);
     if (rc == XC_OK) rc = dev_reserve(c->d_invR, 8 * (size_t)c->natoms * c->natoms);
     if (rc == XC_OK) rc = dev_reserve(c->d_nnhalf, 8 * (size_t)c->natoms);
+    if (rc == XC_OK && c->natoms <= kNbrMaxAtoms) {
+        rc = dev_reserve(c->d_nbr_idx, sizeof(int) * (size_t)c->natoms * c->natoms);
+        if (rc == XC_OK) rc = dev_reserve(c->d_nbr_R, 8 * (size_t)c->natoms * c->natoms);
+    }
     if (rc == XC_OK) rc = upload(c->d_shells, sh.data(), sizeof(ShellDev) * sh.size(), c->stream);
     if (rc == XC_OK) rc = upload(c->d_palpha, c->prim_alpha.data(), 8 * (size_t)po, c->stream);
     if (rc == XC_OK) rc = upload(c->d_fshell, fshell.data(), sizeof(int) * fshell.size(), c->stream);
@@ -478,7 +490,7 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
     size_t pers = 0;
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells,
                             &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
-                            &c->d_fshell, &c->d_flmn, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
+                            &c->d_fshell, &c->d_flmn, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->epart, &c->npart};
     for (const DevBuf* b : bufs) pers += b->cap;

@@ -53,6 +53,31 @@ __global__ void k_atom_pairs(const double4* atoms, int natoms, double a,
     nnhalf[A] = 0.5 * (1.0 - a) * rmin;
 }
 
+// For every atom C, all atoms ordered by distance R_CB (C itself first, with
+// R = 0): a rank sort, one workgroup per atom.
+__global__ void k_atom_neighbours(const double4* atoms, int natoms, int* nbr_idx,
+                                  double* nbr_R) {
+    extern __shared__ double row[];
+    const int C = blockIdx.x;
+    const double4 rc = atoms[C];
+    for (int j = threadIdx.x; j < natoms; j += blockDim.x) {
+        const double4 rb = atoms[j];
+        const double dx = rc.x - rb.x, dy = rc.y - rb.y, dz = rc.z - rb.z;
+        row[j] = (j == C) ? 0.0 : sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < natoms; j += blockDim.x) {
+        const double r = row[j];
+        int rank = 0;
+        for (int k = 0; k < natoms; ++k) {
+            const double q = row[k];
+            rank += (q < r) || (q == r && k < j);
+        }
+        nbr_idx[(size_t)C * natoms + rank] = j;
+        nbr_R[(size_t)C * natoms + rank] = r;
+    }
+}
+
 int launch_shell_setup(xc_context* c) {
     hipLaunchKernelGGL(k_shell_rcut, dim3(grid_1d(c->nshells, 128)), dim3(128), 0,
                        c->stream, (ShellDev*)c->d_shells.p, c->nshells,
@@ -62,6 +87,13 @@ int launch_shell_setup(xc_context* c) {
                        c->stream, (const double4*)c->d_atoms.p, c->natoms, c->ssf_a,
                        (double*)c->d_invR.p, (double*)c->d_nnhalf.p);
     XC_HIP(hipGetLastError());
+    if (c->natoms <= kNbrMaxAtoms) {
+        hipLaunchKernelGGL(k_atom_neighbours, dim3(c->natoms), dim3(256),
+                           sizeof(double) * (size_t)c->natoms, c->stream,
+                           (const double4*)c->d_atoms.p, c->natoms, (int*)c->d_nbr_idx.p,
+                           (double*)c->d_nbr_R.p);
+        XC_HIP(hipGetLastError());
+    }
     return XC_OK;
 }
 
@@ -119,12 +151,34 @@ __device__ inline double dist2_to(const double4& at, double x, double y, double 
 }
 
 // Unnormalised cell product P_C(r) = prod_{B != C} s(mu_CB); stops at zero.
-// An atom B with d_B >= d_C (1 + a)/(1 - a) has mu_CB <= -a (because
-// R_CB <= d_B + d_C), so s(mu_CB) = 1 exactly and it is skipped on its
-// squared distance alone.
-__device__ inline double ssf_product(int C, double dC, const double4* atoms,
-                                     const double* invR, int natoms, double x,
-                                     double y, double z, double a, double far2) {
+// Only atoms with R_CB < 2 d_C / (1 - a) can give a factor other than 1
+// (otherwise d_B >= R_CB - d_C gives mu_CB <= -a, s = 1 exactly), so the
+// loop runs over C's neighbours in order of distance and stops there.
+__device__ inline double ssf_product_nbr(int C, double dC, const double4* atoms,
+                                         const int* nbr_idx, const double* nbr_R,
+                                         int natoms, double x, double y, double z,
+                                         double a, double reach) {
+    double p = 1.0;
+    const int* ni = nbr_idx + (size_t)C * natoms;
+    const double* nr = nbr_R + (size_t)C * natoms;
+    const double lim = dC * reach;
+    for (int t = 1; t < natoms; ++t) {
+        const double R = nr[t];
+        if (R >= lim) break;
+        const int B = ni[t];
+        const double dB = sqrt(dist2_to(atoms[B], x, y, z));
+        p *= ssf_s((dC - dB) / R, a);
+        if (p == 0.0) break;
+    }
+    return p;
+}
+
+// Same product without neighbour lists (very large molecules): atoms B with
+// d_B >= d_C (1 + a)/(1 - a) have mu_CB <= -a and are skipped on their
+// squared distance.
+__device__ inline double ssf_product_all(int C, double dC, const double4* atoms,
+                                         const double* invR, int natoms, double x,
+                                         double y, double z, double a, double far2) {
     double p = 1.0;
     const double* ir = invR + (size_t)C * natoms;
     const double lim2 = dC * dC * far2;
@@ -142,16 +196,18 @@ __device__ inline double ssf_product(int C, double dC, const double4* atoms,
 //  * |r - R_A| < (1-a)/2 min_B R_AB: the parent owns the point (p = 1);
 //  * an atom C with (d_C - d_min) / R_{C,nearest} >= a has s(mu_{C,nearest}) = 0,
 //    hence P_C = 0, and is skipped;
-//  * inside a product, atoms far beyond d_C contribute factors of exactly 1.
-// Atom centres are staged in LDS and read by every lane of a wave together.
-constexpr int kSsfLdsAtoms = 2048;
+//  * inside a product only nearby atoms can differ from 1 (see above).
+// Atom centres are staged in LDS (dynamic size, up to kSsfLdsAtoms so
+// several workgroups still fit on a CU) and read by every lane together.
+constexpr int kSsfLdsAtoms = 512;
 
 __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* gatoms,
                                              const double4* atoms_g, const double* invR,
+                                             const int* nbr_idx, const double* nbr_R,
                                              const double* nnhalf, int natoms, double a,
                                              const double* X, const double* Y,
                                              const double* Z, double* W) {
-    __shared__ double4 sat[kSsfLdsAtoms];
+    extern __shared__ double4 sat[];
     const bool in_lds = natoms <= kSsfLdsAtoms;
     if (in_lds)
         for (int k = threadIdx.x; k < natoms; k += blockDim.x) sat[k] = atoms_g[k];
@@ -165,8 +221,9 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
     const double x = X[i], y = Y[i], z = Z[i];
     const double dA = sqrt(dist2_to(atoms[A], x, y, z));
     if (dA < nnhalf[A]) return;
+    const double reach = 2.0 / (1.0 - a) * (1.0 + 1e-12);
     const double far = (1.0 + a) / (1.0 - a) * (1.0 + 1e-12);
-    const double far2 = far * far;
+    const bool use_nbr = nbr_idx != nullptr;
     double dmin2 = INFINITY;
     int bmin = 0;
     for (int B = 0; B < natoms; ++B) {
@@ -177,13 +234,15 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
         }
     }
     const double dmin = sqrt(dmin2);
-    const double PA = ssf_product(A, dA, atoms, invR, natoms, x, y, z, a, far2);
+    const double PA = use_nbr
+        ? ssf_product_nbr(A, dA, atoms, nbr_idx, nbr_R, natoms, x, y, z, a, reach)
+        : ssf_product_all(A, dA, atoms, invR, natoms, x, y, z, a, far * far);
     if (PA == 0.0) {
         W[i] = 0.0;
         return;
     }
     // candidates C need d_C < d_min + a R_{C,nearest} <= d_min + a (d_C + d_min)
-    const double cand = dmin * (1.0 + a) / (1.0 - a) * (1.0 + 1e-12);
+    const double cand = dmin * far;
     const double cand2 = cand * cand;
     double sum = 0.0;
     for (int C = 0; C < natoms; ++C) {
@@ -195,7 +254,9 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
         if (C != bmin && dC2 >= cand2) continue;
         const double dC = sqrt(dC2);
         if (C != bmin && (dC - dmin) * invR[(size_t)C * natoms + bmin] >= a) continue;
-        sum += ssf_product(C, dC, atoms, invR, natoms, x, y, z, a, far2);
+        sum += use_nbr
+            ? ssf_product_nbr(C, dC, atoms, nbr_idx, nbr_R, natoms, x, y, z, a, reach)
+            : ssf_product_all(C, dC, atoms, invR, natoms, x, y, z, a, far * far);
     }
     W[i] = w * (PA / sum);
 }
@@ -203,10 +264,13 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
 int launch_ssf(xc_context* c) {
     PhaseScope ps(c, XC_PHASE_WEIGHTS);
     const int npa = c->n_rad * c->n_ang;
-    hipLaunchKernelGGL(k_ssf, dim3(grid_1d(c->n_nominal, 256)), dim3(256), 0, c->stream,
+    const size_t lds = c->natoms <= kSsfLdsAtoms ? sizeof(double4) * (size_t)c->natoms : 0;
+    hipLaunchKernelGGL(k_ssf, dim3(grid_1d(c->n_nominal, 256)), dim3(256), lds, c->stream,
                        c->n_nominal, npa, (const int*)c->d_gatoms.p,
                        (const double4*)c->d_atoms.p, (const double*)c->d_invR.p,
-                       (const double*)c->d_nnhalf.p, c->natoms, c->ssf_a,
+                       c->natoms <= kNbrMaxAtoms ? (const int*)c->d_nbr_idx.p : nullptr,
+                       (const double*)c->d_nbr_R.p, (const double*)c->d_nnhalf.p,
+                       c->natoms, c->ssf_a,
                        (const double*)c->raw_x.p, (const double*)c->raw_y.p,
                        (const double*)c->raw_z.p, (double*)c->raw_w.p);
     XC_HIP(hipGetLastError());

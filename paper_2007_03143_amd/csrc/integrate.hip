@@ -265,6 +265,15 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
 
+    // 16 x 16 output blocks made only of padding rows or columns are skipped
+    // (wave-uniform)
+    bool live[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+            live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + wn * 32 + nb * 16 < B.ng);
+
     const int nk = B.nbp / 16;
     fload(0);
     gload(0);
@@ -289,7 +298,8 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = M::mma(a[mb], b[nb], acc[mb][nb]);
+                for (int nb = 0; nb < 2; ++nb)
+                    if (live[mb][nb]) acc[mb][nb] = M::mma(a[mb], b[nb], acc[mb][nb]);
         }
         if (ks + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
@@ -518,7 +528,18 @@ __global__ __launch_bounds__(256) void k_syr2k(
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
 
-    const int nk = B.ngp / KS;
+    // the points beyond n_g are zero padding: K runs to n_g rounded up to KS
+    const int nk = (B.ng + KS - 1) / KS;
+    // skip 16 x 16 blocks that are padding or lie above the diagonal
+    bool live[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int r0 = I * kTile + wm * 32 + mb * 16;
+            const int c0 = J * kTile + wn * 32 + nb * 16;
+            live[mb][nb] = (r0 < B.nb) && (c0 < B.nb) && (c0 <= r0 + 15);
+        }
     gload(0);
     sstore(0);
     __syncthreads();
@@ -545,6 +566,7 @@ __global__ __launch_bounds__(256) void k_syr2k(
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb) {
+                    if (!live[mb][nb]) continue;
                     acc[mb][nb] = M::mma(az[mb], bp[nb], acc[mb][nb]);
                     acc[mb][nb] = M::mma(ap[mb], bz[nb], acc[mb][nb]);
                 }

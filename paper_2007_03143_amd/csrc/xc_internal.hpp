@@ -38,6 +38,7 @@ constexpr int kMaxBatch = 1024;     // largest batch_max accepted
 constexpr int kTile = 64;           // contraction tile edge (rows and columns)
 constexpr int kRowPad = 16;         // n_b is stored padded to a multiple of this
 constexpr int kColPad = 64;         // n_g is stored padded to a multiple of this
+constexpr int kNbrMaxAtoms = 4096;  // distance-ordered neighbour lists up to this many atoms
 
 // One basis shell as the kernels read it.
 struct ShellDev {
@@ -153,6 +154,7 @@ struct xc_context {
     // device inputs
     xc::DevBuf d_atoms, d_invR, d_nnhalf, d_shells, d_palpha, d_pcoef, d_ang, d_gatoms;
     xc::DevBuf d_fshell, d_flmn;
+    xc::DevBuf d_nbr_idx, d_nbr_R;  // per atom: all atoms by distance
 
     // grid and batches
     bool built = false;

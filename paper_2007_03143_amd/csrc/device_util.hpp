@@ -70,6 +70,16 @@ __device__ inline int find_segment(const int* prefix, int n, int t) {
     return lo;
 }
 
+// Pointers that kernels read out of device-side descriptors are generic to
+// the compiler, so their loads and atomics become flat instructions. Flat
+// operations also count against the LDS wait counter: a wait for LDS data
+// then also waits for every global load in flight, which defeats
+// prefetching. Typed global pointers keep these accesses on the global path.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> to_global(T* p) {
+    return (gptr<T>)p;
+}
+
 inline unsigned grid_1d(long long n, int block) {
     return (unsigned)((n + block - 1) / block);
 }

@@ -166,8 +166,11 @@ __device__ inline double ssf_product_nbr(int C, double dC, const double4* atoms,
         const double R = nr[t];
         if (R >= lim) break;
         const int B = ni[t];
-        const double dB = sqrt(dist2_to(atoms[B], x, y, z));
-        p *= ssf_s((dC - dB) / R, a);
+        // s(mu_CB) = 1 unless d_B < d_C + a R_CB: test on the squared distance
+        const double d2 = dist2_to(atoms[B], x, y, z);
+        const double edge = dC + a * R * (1.0 + 1e-12);
+        if (d2 >= edge * edge) continue;
+        p *= ssf_s((dC - sqrt(d2)) / R, a);
         if (p == 0.0) break;
     }
     return p;
@@ -198,9 +201,12 @@ __device__ inline double ssf_product_all(int C, double dC, const double4* atoms,
 //    hence P_C = 0, and is skipped;
 //  * inside a product only nearby atoms can differ from 1 (see above).
 // Atom centres are staged in LDS (dynamic size, up to kSsfLdsAtoms so
-// several workgroups still fit on a CU) and read by every lane together.
+// several workgroups still fit on a CU) and read by every lane together;
+// larger molecules read them from global memory. The two cases are separate
+// instantiations so that every access has a known address space.
 constexpr int kSsfLdsAtoms = 512;
 
+template <bool kInLds>
 __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* gatoms,
                                              const double4* atoms_g, const double* invR,
                                              const int* nbr_idx, const double* nbr_R,
@@ -208,11 +214,11 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
                                              const double* X, const double* Y,
                                              const double* Z, double* W) {
     extern __shared__ double4 sat[];
-    const bool in_lds = natoms <= kSsfLdsAtoms;
-    if (in_lds)
+    if (kInLds) {
         for (int k = threadIdx.x; k < natoms; k += blockDim.x) sat[k] = atoms_g[k];
-    __syncthreads();
-    const double4* atoms = in_lds ? sat : atoms_g;
+        __syncthreads();
+    }
+    const double4* atoms = kInLds ? sat : atoms_g;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double w = W[i];
@@ -224,16 +230,35 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
     const double reach = 2.0 / (1.0 - a) * (1.0 + 1e-12);
     const double far = (1.0 + a) / (1.0 - a) * (1.0 + 1e-12);
     const bool use_nbr = nbr_idx != nullptr;
-    double dmin2 = INFINITY;
-    int bmin = 0;
+    // the four nearest atoms (squared distances, ascending)
+    constexpr int kNear = 4;
+    double nd2[kNear];
+    int nb[kNear];
+#pragma unroll
+    for (int k = 0; k < kNear; ++k) {
+        nd2[k] = INFINITY;
+        nb[k] = -1;
+    }
     for (int B = 0; B < natoms; ++B) {
-        const double d2 = dist2_to(atoms[B], x, y, z);
-        if (d2 < dmin2) {
-            dmin2 = d2;
-            bmin = B;
+        double d2 = dist2_to(atoms[B], x, y, z);
+        int b = B;
+#pragma unroll
+        for (int k = 0; k < kNear; ++k) {
+            if (d2 < nd2[k]) {
+                const double td = nd2[k];
+                const int tb = nb[k];
+                nd2[k] = d2;
+                nb[k] = b;
+                d2 = td;
+                b = tb;
+            }
         }
     }
-    const double dmin = sqrt(dmin2);
+    const int bmin = nb[0];
+    const double dmin = sqrt(nd2[0]);
+    double nd[kNear];
+#pragma unroll
+    for (int k = 0; k < kNear; ++k) nd[k] = sqrt(nd2[k]);
     const double PA = use_nbr
         ? ssf_product_nbr(A, dA, atoms, nbr_idx, nbr_R, natoms, x, y, z, a, reach)
         : ssf_product_all(A, dA, atoms, invR, natoms, x, y, z, a, far * far);
@@ -253,7 +278,14 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
         const double dC2 = dist2_to(atoms[C], x, y, z);
         if (C != bmin && dC2 >= cand2) continue;
         const double dC = sqrt(dC2);
-        if (C != bmin && (dC - dmin) * invR[(size_t)C * natoms + bmin] >= a) continue;
+        // P_C = 0 if s(mu_CB) = 0 for one of the nearest atoms B
+        bool zero = false;
+#pragma unroll
+        for (int k = 0; k < kNear; ++k)
+            if (nb[k] >= 0 && nb[k] != C &&
+                (dC - nd[k]) * invR[(size_t)C * natoms + nb[k]] >= a)
+                zero = true;
+        if (zero) continue;
         sum += use_nbr
             ? ssf_product_nbr(C, dC, atoms, nbr_idx, nbr_R, natoms, x, y, z, a, reach)
             : ssf_product_all(C, dC, atoms, invR, natoms, x, y, z, a, far * far);
@@ -264,8 +296,10 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
 int launch_ssf(xc_context* c) {
     PhaseScope ps(c, XC_PHASE_WEIGHTS);
     const int npa = c->n_rad * c->n_ang;
-    const size_t lds = c->natoms <= kSsfLdsAtoms ? sizeof(double4) * (size_t)c->natoms : 0;
-    hipLaunchKernelGGL(k_ssf, dim3(grid_1d(c->n_nominal, 256)), dim3(256), lds, c->stream,
+    const bool in_lds = c->natoms <= kSsfLdsAtoms;
+    const size_t lds = in_lds ? sizeof(double4) * (size_t)c->natoms : 0;
+    hipLaunchKernelGGL(in_lds ? k_ssf<true> : k_ssf<false>, dim3(grid_1d(c->n_nominal, 256)),
+                       dim3(256), lds, c->stream,
                        c->n_nominal, npa, (const int*)c->d_gatoms.p,
                        (const double4*)c->d_atoms.p, (const double*)c->d_invR.p,
                        c->natoms <= kNbrMaxAtoms ? (const int*)c->d_nbr_idx.p : nullptr,

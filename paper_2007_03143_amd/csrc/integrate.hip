@@ -50,12 +50,59 @@ template <> struct Mfma<float> {
     __device__ static inline int acc_row(int r, int lane) { return 4 * (lane >> 4) + r; }
 };
 
+// The request descriptor with every array typed as global memory.
+struct ReqG {
+    gptr<const ShellDev> shells;
+    gptr<const double> palpha, pcoef;
+    gptr<const int> shell_list, shell_loff, func_list, func_shell, func_lmn;
+    gptr<const double> px, py, pz, pw, P;
+    gptr<double> V, epart, npart;
+    double rho_thresh;
+    int nbf;
+};
+
+__device__ inline ReqG global_view(const ReqDev& r) {
+    ReqG g;
+    g.shells = to_global(r.shells);
+    g.palpha = to_global(r.palpha);
+    g.pcoef = to_global(r.pcoef);
+    g.shell_list = to_global(r.shell_list);
+    g.shell_loff = to_global(r.shell_loff);
+    g.func_list = to_global(r.func_list);
+    g.func_shell = to_global(r.func_shell);
+    g.func_lmn = to_global(r.func_lmn);
+    g.px = to_global(r.px);
+    g.py = to_global(r.py);
+    g.pz = to_global(r.pz);
+    g.pw = to_global(r.pw);
+    g.P = to_global(r.P);
+    g.V = to_global(r.V);
+    g.epart = to_global(r.epart);
+    g.npart = to_global(r.npart);
+    g.rho_thresh = r.rho_thresh;
+    g.nbf = r.nbf;
+    return g;
+}
+
+__device__ inline ShellDev load_shell(gptr<const ShellDev> p) {
+    ShellDev s;
+    s.x = p->x;
+    s.y = p->y;
+    s.z = p->z;
+    s.rcut2 = p->rcut2;
+    s.L = p->L;
+    s.nprim = p->nprim;
+    s.prim_off = p->prim_off;
+    s.first_func = p->first_func;
+    return s;
+}
+
 // ------------------------------------------------------------ collocation --
 // Radial part of a shell at squared distance r2: rad = sum_xi d e^{-alpha r2}
 // and drad = -2 sum_xi alpha d e^{-alpha r2} (d rad / d r2 times 2), zero
 // outside the cutoff sphere.
-__device__ inline void shell_radial(const ShellDev& sh, const double* palpha,
-                                    const double* pcoef, double r2, double& rad,
+__device__ inline void shell_radial(const ShellDev& sh, gptr<const double> palpha,
+                                    gptr<const double> pcoef, double r2, double& rad,
                                     double& drad) {
     rad = 0.0;
     drad = 0.0;
@@ -147,7 +194,7 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
                                                 const ReqDev* __restrict__ reqs,
                                                 char* __restrict__ scratch) {
     const WaveBatch B = wb[blockIdx.x];
-    const ReqDev R = reqs[B.req];
+    const ReqG R = global_view(reqs[B.req]);
     __shared__ double sx[kMaxBatch], sy[kMaxBatch], sz[kMaxBatch];
     for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
         const bool v = i < B.ng;
@@ -164,7 +211,7 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
     for (int sl = wave; sl < B.nshell; sl += 4) {
         const int s = R.shell_list[B.shell_off + sl];
         const int loff = R.shell_loff[B.shell_off + sl];
-        const ShellDev sh = R.shells[s];
+        const ShellDev sh = load_shell(R.shells + s);
         for (int i = lane; i < B.ngp; i += 64) {
             double dx, dy, dz, rad, drad;
             const double r2 = dist2_nc(sx[i], sy[i], sz[i], sh, dx, dy, dz);
@@ -197,16 +244,16 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int bi = find_segment(prefix, nwb, t);
     const WaveBatch B = wb[bi];
-    const ReqDev& R = reqs[B.req];
-    const double* __restrict__ P = R.P;
+    const ReqG R = global_view(reqs[B.req]);
+    const gptr<const double> P = R.P;
     const int nbf = R.nbf;
-    const int* __restrict__ func_list = R.func_list;
+    const gptr<const int> func_list = R.func_list;
     const int lt = t - prefix[bi];
     const int ntn = B.ngp / kTile;
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
     const T* Phi = (const T*)(scratch + 8 * B.phi_off);
-    const int* fl = func_list + B.func_off;
+    const gptr<const int> fl = func_list + B.func_off;
 
     // operand tiles during the main loop, the X tile in the epilogue
     constexpr int kABytes = 2 * kTile * 17 * (int)sizeof(T);
@@ -232,7 +279,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int ar = tid >> 2, ac = (tid & 3) * 4;
     const int br = tid >> 4, bc = (tid & 15) * 4;
     const int fr = frow[ar];
-    const double* Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
+    const gptr<const double> Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
 
     // The P^j columns of a K step are gathered through the function list;
     // those indices are fetched one step ahead of the P loads that use them
@@ -329,7 +376,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
             if (m0 + rl >= B.nb) break;
             const int sidx = fsh[rl];
             if (sidx != prev) {
-                const ShellDev sh = R.shells[sidx];
+                const ShellDev sh = load_shell(R.shells + sidx);
                 const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
                 shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
                 prev = sidx;
@@ -378,8 +425,8 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
                                                 const ReqDev* __restrict__ reqs,
                                                 char* __restrict__ scratch) {
     const WaveBatch B = wb[blockIdx.x];
-    const ReqDev& R = reqs[B.req];
-    const double* __restrict__ W = R.pw;
+    const ReqG R = global_view(reqs[B.req]);
+    const gptr<const double> W = R.pw;
     const double rho_thresh = R.rho_thresh;
     __shared__ double sa[kMaxBatch], sbx[kMaxBatch], sby[kMaxBatch], sbz[kMaxBatch];
     __shared__ double red[256];
@@ -440,7 +487,7 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
     for (int sl = wave; sl < B.nshell; sl += 4) {
         const int sidx = R.shell_list[B.shell_off + sl];
         const int loff = R.shell_loff[B.shell_off + sl];
-        const ShellDev sh = R.shells[sidx];
+        const ShellDev sh = load_shell(R.shells + sidx);
         for (int i = lane; i < B.ngp; i += 64) {
             double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
             if (i < B.ng) {
@@ -472,9 +519,9 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int bi = find_segment(prefix, nwb, t);
     const WaveBatch B = wb[bi];
-    const ReqDev& R = reqs[B.req];
-    const int* __restrict__ func_list = R.func_list;
-    double* __restrict__ V = R.V;
+    const ReqG R = global_view(reqs[B.req]);
+    const gptr<const int> func_list = R.func_list;
+    const gptr<double> V = R.V;
     const int nbf = R.nbf;
     const int lt = t - prefix[bi];
     int I = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);
@@ -484,7 +531,7 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const size_t slab = (size_t)B.nbp * B.ngp;
     const T* Phi = (const T*)(scratch + 8 * B.phi_off);
     const T* Zm = Phi + slab;
-    const int* fl = func_list + B.func_off;
+    const gptr<const int> fl = func_list + B.func_off;
 
     // K steps of 8 keep the four double-buffered operand tiles at 37 KB of
     // LDS, so four workgroups fit on a CU.
@@ -580,12 +627,13 @@ __global__ __launch_bounds__(256) void k_syr2k(
         for (int r = 0; r < 4; ++r) {
             const int row = I * kTile + wm * 32 + mb * 16 + M::acc_row(r, lane);
             if (row >= B.nb) continue;
-            double* vrow = V + (size_t)fl[row] * nbf;
+            const gptr<double> vrow = V + (size_t)fl[row] * nbf;
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
                 const int col = J * kTile + wn * 32 + nb * 16 + (lane & 15);
                 if (col < B.nb && col <= row)
-                    unsafeAtomicAdd(vrow + fl[col], double(acc[mb][nb][r]));
+                    __hip_atomic_fetch_add(vrow + fl[col], double(acc[mb][nb][r]),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }

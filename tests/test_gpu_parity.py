@@ -167,6 +167,22 @@ def test_cluster_sampled_atoms_parity(atom):
     _check(w, "pbe", atom_mask=mask)
 
 
+def test_chain600_sampled_atoms_parity():
+    """The 600-atom polypeptide-like chain (6280 functions with the diffuse
+    shell): more atoms than the SSF kernel stages in LDS and a large P. The
+    radial x angular grid is reduced (30 x 50) so that the oracle's all-pairs
+    partition over the two sampled parent atoms (a C and an H) stays short;
+    the GPU still builds, partitions and batches every atom's grid."""
+    from workloads import cfg_chain
+    say("case chain600 build workload")
+    w = cfg_chain(n_rad=30, n_ang=50)
+    mask = np.zeros(w.natoms, np.uint8)
+    heavy = int(np.nonzero(w.mol.Z == 6)[0][3])
+    light = int(np.nonzero(w.mol.Z == 1)[0][7])
+    mask[[heavy, light]] = 1
+    _check(w, "pbe", atom_mask=mask)
+
+
 @pytest.mark.parametrize("functional", ["lda", "pbe"])
 def test_mixed_fp32_error_vs_oracle(functional):
     """FP32 collocation and contractions, FP64 functional and sums: errors

@@ -190,24 +190,27 @@ def overlap_matrix(basis, coords, chunk=200000):
                 AB2 = ((RA - RB) ** 2).sum(axis=1)
                 blk = np.zeros((pa.shape[0], len(ca), len(cb)))
                 for xi in range(maxp):
-                    a = A[pa, xi]
-                    da = D[pa, xi]
                     for eta in range(maxp):
-                        b = A[pb, eta]
-                        db = D[pb, eta]
-                        w = da * db
-                        if not np.any(w):
+                        a_all, b_all = A[pa, xi], A[pb, eta]
+                        w_all = D[pa, xi] * D[pb, eta]
+                        # pairs whose Gaussian prefactor underflows to exactly 0
+                        # (exponent beyond 746) add exactly nothing: skip them
+                        keep = np.nonzero((w_all != 0.0) & (
+                            a_all * b_all / (a_all + b_all) * AB2 < 746.0))[0]
+                        if keep.size == 0:
                             continue
+                        a, b, w = a_all[keep], b_all[keep], w_all[keep]
+                        RAk, RBk = RA[keep], RB[keep]
                         p = a + b
-                        pref = w * np.exp(-a * b / p * AB2)
-                        Pc = (a[:, None] * RA + b[:, None] * RB) / p[:, None]
-                        PA, PB = Pc - RA, Pc - RB
+                        pref = w * np.exp(-a * b / p * AB2[keep])
+                        Pc = (a[:, None] * RAk + b[:, None] * RBk) / p[:, None]
+                        PA, PB = Pc - RAk, Pc - RBk
                         # one-dimensional overlaps I[axis][l1][l2]
-                        I = np.zeros((3, La + 1, Lb + 1, pa.shape[0]))
+                        I = np.zeros((3, La + 1, Lb + 1, keep.size))
                         for ax in range(3):
                             for l1 in range(La + 1):
                                 for l2 in range(Lb + 1):
-                                    acc = np.zeros(pa.shape[0])
+                                    acc = np.zeros(keep.size)
                                     for i in range(l1 + 1):
                                         for j in range(l2 + 1):
                                             t = i + j
@@ -220,9 +223,9 @@ def overlap_matrix(basis, coords, chunk=200000):
                                     I[ax, l1, l2] = acc
                         for u, (l1, m1, n1) in enumerate(ca):
                             for v, (l2, m2, n2) in enumerate(cb):
-                                blk[:, u, v] += (pref * I[0, l1, l2]
-                                                 * I[1, m1, m2] * I[2, n1, n2])
-                for k in range(pa.shape[0]):
-                    i0, j0 = ff[pa[k]], ff[pb[k]]
-                    S[i0:i0 + len(ca), j0:j0 + len(cb)] = blk[k]
+                                blk[keep, u, v] += (pref * I[0, l1, l2]
+                                                    * I[1, m1, m2] * I[2, n1, n2])
+                rows = ff[pa][:, None, None] + np.arange(len(ca))[None, :, None]
+                cols = ff[pb][:, None, None] + np.arange(len(cb))[None, None, :]
+                S[rows, cols] = blk
     return S

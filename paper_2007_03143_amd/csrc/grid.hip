@@ -293,9 +293,129 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
     W[i] = w * (PA / sum);
 }
 
+// ------------------------------------------- partition, one wave a point --
+// For molecules up to kSsfWaveMaxAtoms atoms. The lanes of a wave first test
+// one point each (zero weight, shortcut). The wave then takes the remaining
+// points one at a time and spreads each cell product over the atoms, lane l
+// holding atoms l, l + 64, ...: every lane does the same work whatever the
+// point, the rows of 1/R_CB are read coalesced, and the product is finished
+// by a butterfly over the wave. The atoms C that can share a point are those
+// with d_C < d_min (1 + a)/(1 - a) whose factor against the nearest atom is
+// not zero; every other P_C is exactly zero.
+constexpr int kSsfWaveMaxAtoms = 1024;
+
+__device__ inline double wave_product(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NPER>
+__global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const int* gatoms,
+                                                  const double4* atoms_g, const double* invR,
+                                                  const double* nnhalf, int natoms, double a,
+                                                  const double* X, const double* Y,
+                                                  const double* Z, double* W) {
+    extern __shared__ double4 sat[];
+    for (int k = threadIdx.x; k < natoms; k += blockDim.x) sat[k] = atoms_g[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double x = 0.0, y = 0.0, z = 0.0, w = 0.0;
+    int A = 0;
+    bool need = false;
+    if (i < n && natoms > 1) {
+        w = W[i];
+        if (w != 0.0) {
+            A = gatoms[(int)(i / npa)];
+            x = X[i];
+            y = Y[i];
+            z = Z[i];
+            need = !(sqrt(dist2_to(sat[A], x, y, z)) < nnhalf[A]);
+        }
+    }
+    const double far = (1.0 + a) / (1.0 - a) * (1.0 + 1e-12);
+    unsigned long long todo = __ballot(need);
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const double px = __shfl(x, l, 64), py = __shfl(y, l, 64), pz = __shfl(z, l, 64);
+        const int pA = __shfl(A, l, 64);
+        // this lane's atoms: distances, and the nearest atom over the wave
+        double d[NPER];
+        double dmin = INFINITY;
+        int bmin = natoms;
+#pragma unroll
+        for (int j = 0; j < NPER; ++j) {
+            const int B = lane + 64 * j;
+            d[j] = B < natoms ? sqrt(dist2_to(sat[B], px, py, pz)) : INFINITY;
+            if (d[j] < dmin) {
+                dmin = d[j];
+                bmin = B;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double od = __shfl_xor(dmin, o, 64);
+            const int ob = __shfl_xor(bmin, o, 64);
+            if (od < dmin || (od == dmin && ob < bmin)) {
+                dmin = od;
+                bmin = ob;
+            }
+        }
+        // P_C = prod_{B != C} s(mu_CB), spread over the lanes
+        auto cell = [&](int C) {
+            const double dC = sqrt(dist2_to(sat[C], px, py, pz));
+            const double* ir = invR + (size_t)C * natoms;
+            double p = 1.0;
+#pragma unroll
+            for (int j = 0; j < NPER; ++j) {
+                const int B = lane + 64 * j;
+                if (B < natoms && B != C) p *= ssf_s((dC - d[j]) * ir[B], a);
+            }
+            return wave_product(p);
+        };
+        const double PA = cell(pA);
+        double frac = 0.0;
+        if (PA != 0.0) {
+            double sum = PA;
+            const double cand = dmin * far;
+#pragma unroll
+            for (int j = 0; j < NPER; ++j) {
+                const int C = lane + 64 * j;
+                bool c = C < natoms && C != pA && (C == bmin || d[j] < cand);
+                if (c && C != bmin && bmin < natoms)
+                    c = (d[j] - dmin) * invR[(size_t)C * natoms + bmin] < a;
+                unsigned long long cm = __ballot(c);
+                while (cm) {
+                    const int lc = __ffsll((unsigned long long)cm) - 1;
+                    cm &= cm - 1;
+                    sum += cell(lc + 64 * j);
+                }
+            }
+            frac = PA / sum;
+        }
+        if (lane == l) W[i] = w * frac;
+    }
+}
+
 int launch_ssf(xc_context* c) {
     PhaseScope ps(c, XC_PHASE_WEIGHTS);
     const int npa = c->n_rad * c->n_ang;
+    if (c->natoms <= kSsfWaveMaxAtoms) {
+        const int nper = (c->natoms + 63) / 64;
+        auto k = nper <= 1 ? k_ssf_wave<1> : nper <= 2 ? k_ssf_wave<2>
+               : nper <= 4 ? k_ssf_wave<4> : nper <= 8 ? k_ssf_wave<8> : k_ssf_wave<16>;
+        hipLaunchKernelGGL(k, dim3(grid_1d(c->n_nominal, 256)), dim3(256),
+                           sizeof(double4) * (size_t)c->natoms, c->stream, c->n_nominal, npa,
+                           (const int*)c->d_gatoms.p, (const double4*)c->d_atoms.p,
+                           (const double*)c->d_invR.p, (const double*)c->d_nnhalf.p,
+                           c->natoms, c->ssf_a, (const double*)c->raw_x.p,
+                           (const double*)c->raw_y.p, (const double*)c->raw_z.p,
+                           (double*)c->raw_w.p);
+        XC_HIP(hipGetLastError());
+        return XC_OK;
+    }
     const bool in_lds = c->natoms <= kSsfLdsAtoms;
     const size_t lds = in_lds ? sizeof(double4) * (size_t)c->natoms : 0;
     hipLaunchKernelGGL(in_lds ? k_ssf<true> : k_ssf<false>, dim3(grid_1d(c->n_nominal, 256)),

@@ -205,7 +205,16 @@ def main():
         ms_m = (time.perf_counter() - t4) * 1e3 / args.steps
         ENm = ctx.EN.cpu().numpy()
         Vm = ctx.V.cpu().numpy()
+        # phase split of the same integration, timed separately with HIP events
+        ctx.set_timing(True)
+        for i in range(args.steps):
+            ctx.integrate(P, functional, prec)
+        torch.cuda.synchronize()
+        tm = ctx.timing()
+        ctx.set_timing(False)
         mixed[prec] = {"warm_value": n_nom / (ms_m * 1e-3), "warm_ms_per_step": ms_m,
+                       "phase_ms_per_step": {k: v["ms"] / args.steps for k, v in tm.items()
+                                             if v["launches"]},
                        "speedup_vs_fp64_warm": ms_warm / ms_m,
                        "dE_xc_vs_fp64": float(ENm[0] - EN[0]),
                        "dN_e_vs_fp64": float(ENm[1] - EN[1]),

@@ -265,9 +265,30 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     T (*Bs)[16][kTile + 1] = reinterpret_cast<T (*)[16][kTile + 1]>(lds + kABytes);
     double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
     __shared__ int frow[kTile], fsh[kTile], flmn[kTile];
+    // function indices (columns of P) of two consecutive K steps
+    __shared__ __attribute__((aligned(16))) int sfl[2][16];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    const int nk = B.nbp / 16;
+    // The 16 column indices of a K step are loaded once, by threads 0-15,
+    // two steps ahead, and passed on through LDS.
+    int fnext = -1;
+    auto fetch = [&](int ks) {
+        if (tid < 16) {
+            const int k = ks * 16 + tid;
+            fnext = k < B.nb ? fl[k] : -1;
+        }
+    };
+    auto fput = [&](int slot) {
+        if (tid < 16) sfl[slot][tid] = fnext;
+    };
+    fetch(0);
+    fput(0);
+    if (nk > 1) {
+        fetch(1);
+        fput(1);
+    }
     if (tid < kTile) {
         const int f = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
         frow[tid] = f;
@@ -281,24 +302,39 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int fr = frow[ar];
     const gptr<const double> Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
 
-    // The P^j columns of a K step are gathered through the function list;
-    // those indices are fetched one step ahead of the P loads that use them
-    // so the two dependent global loads never sit back to back.
+    // The P^j columns of a K step are gathered through the function list.
     T ra[4], rb[4];
     int fc[4];
-    auto fload = [&](int ks) {
-        const int k0 = ks * 16 + ac;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fc[q] = (k0 + q < B.nb) ? fl[k0 + q] : -1;
+    auto fread = [&](int ks) {
+        const int4 v = *reinterpret_cast<const int4*>(&sfl[ks & 1][ac]);
+        fc[0] = v.x;
+        fc[1] = v.y;
+        fc[2] = v.z;
+        fc[3] = v.w;
     };
+    // FP32: the P values stay FP64 in registers until the LDS store, where
+    // they are rounded and the padding is selected away; all four loads go
+    // to valid (clamped) addresses. (A conversion right after each load, in
+    // a branch around it, made every load wait for the one before.)
+    double pv[4];
     auto gload = [&](int ks) {
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ra[q] = (fr >= 0 && fc[q] >= 0) ? T(Prow[fc[q]]) : T(0);
+            for (int q = 0; q < 4; ++q) pv[q] = Prow[fc[q] >= 0 ? fc[q] : 0];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ra[q] = (fr >= 0 && fc[q] >= 0) ? T(Prow[fc[q]]) : T(0);
+        }
         const T* src = Phi + (size_t)(ks * 16 + br) * B.ngp + n0 + bc;
 #pragma unroll
         for (int q = 0; q < 4; ++q) rb[q] = src[q];
     };
     auto sstore = [&](int buf) {
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ra[q] = (fr >= 0 && fc[q] >= 0) ? T(pv[q]) : T(0);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             As[buf][ar][ac + q] = ra[q];
@@ -321,17 +357,16 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         for (int nb = 0; nb < 2; ++nb)
             live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + wn * 32 + nb * 16 < B.ng);
 
-    const int nk = B.nbp / 16;
-    fload(0);
+    fread(0);
     gload(0);
     sstore(0);
-    if (nk > 1) fload(1);
+    if (nk > 2) fetch(2);
     __syncthreads();
     for (int ks = 0; ks < nk; ++ks) {
         const int cur = ks & 1;
         if (ks + 1 < nk) {
+            fread(ks + 1);
             gload(ks + 1);
-            if (ks + 2 < nk) fload(ks + 2);
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -349,6 +384,12 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
                     if (live[mb][nb]) acc[mb][nb] = M::mma(a[mb], b[nb], acc[mb][nb]);
         }
         if (ks + 1 < nk) sstore(cur ^ 1);
+        // slot ks & 1 was last read in the previous step: refill it with the
+        // indices of step ks + 2, then start the load for step ks + 3
+        if (ks + 2 < nk) {
+            fput(ks & 1);
+            if (ks + 3 < nk) fetch(ks + 3);
+        }
         __syncthreads();
     }
 
@@ -536,10 +577,22 @@ __global__ __launch_bounds__(256) void k_syr2k(
     // K steps of 8 keep the four double-buffered operand tiles at 37 KB of
     // LDS, so four workgroups fit on a CU.
     constexpr int KS = 8;
-    __shared__ T sZI[2][kTile][KS + 1], sPI[2][kTile][KS + 1];
-    __shared__ T sPJ[2][kTile][KS + 1], sZJ[2][kTile][KS + 1];
+    // row pitch: 9 doubles, or 12 floats (the 4-byte operand reads of a wave
+    // then fall in distinct banks)
+    constexpr int KP = sizeof(T) == 8 ? KS + 1 : KS + 4;
+    __shared__ T sZI[2][kTile][KP], sPI[2][kTile][KP];
+    __shared__ T sPJ[2][kTile][KP], sZJ[2][kTile][KP];
+    // global function indices of the tile's rows and columns (-1: padding)
+    __shared__ int sfI[kTile], sfJ[kTile];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < kTile) {
+        const int r = I * kTile + tid;
+        sfI[tid] = r < B.nb ? fl[r] : -1;
+    } else if (tid < 2 * kTile) {
+        const int r = J * kTile + tid - kTile;
+        sfJ[tid - kTile] = r < B.nb ? fl[r] : -1;
+    }
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = tid >> 2, lc = (tid & 3) * 2;
     const int rI = I * kTile + lr, rJ = J * kTile + lr;
@@ -549,15 +602,36 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const T* zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
     const T* pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
 
+    // FP32: loads from the clamped (always valid) rows, padding rows zeroed
+    // after the load, so no branch separates the loads (with a branch around
+    // each, the 4-byte loads were issued and waited for one at a time). FP64:
+    // rows past the padded count are not loaded at all.
     T g[4][2];
     auto gload = [&](int ks) {
         const int k0 = ks * KS + lc;
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            g[0][q] = vI ? zI[k0 + q] : T(0);
-            g[1][q] = vI ? pI[k0 + q] : T(0);
-            g[2][q] = vJ ? pJ[k0 + q] : T(0);
-            g[3][q] = vJ ? zJ[k0 + q] : T(0);
+            for (int q = 0; q < 2; ++q) {
+                g[0][q] = zI[k0 + q];
+                g[1][q] = pI[k0 + q];
+                g[2][q] = pJ[k0 + q];
+                g[3][q] = zJ[k0 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                g[0][q] = vI ? g[0][q] : T(0);
+                g[1][q] = vI ? g[1][q] : T(0);
+                g[2][q] = vJ ? g[2][q] : T(0);
+                g[3][q] = vJ ? g[3][q] : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                g[0][q] = vI ? zI[k0 + q] : T(0);
+                g[1][q] = vI ? pI[k0 + q] : T(0);
+                g[2][q] = vJ ? pJ[k0 + q] : T(0);
+                g[3][q] = vJ ? zJ[k0 + q] : T(0);
+            }
         }
     };
     auto sstore = [&](int buf) {
@@ -625,14 +699,16 @@ __global__ __launch_bounds__(256) void k_syr2k(
     for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = I * kTile + wm * 32 + mb * 16 + M::acc_row(r, lane);
+            const int tr = wm * 32 + mb * 16 + M::acc_row(r, lane);
+            const int row = I * kTile + tr;
             if (row >= B.nb) continue;
-            const gptr<double> vrow = V + (size_t)fl[row] * nbf;
+            const gptr<double> vrow = V + (size_t)sfI[tr] * nbf;
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
-                const int col = J * kTile + wn * 32 + nb * 16 + (lane & 15);
+                const int tc = wn * 32 + nb * 16 + (lane & 15);
+                const int col = J * kTile + tc;
                 if (col < B.nb && col <= row)
-                    __hip_atomic_fetch_add(vrow + fl[col], double(acc[mb][nb][r]),
+                    __hip_atomic_fetch_add(vrow + sfJ[tc], double(acc[mb][nb][r]),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }

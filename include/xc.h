@@ -59,6 +59,10 @@ extern "C" {
                                 accumulate); FP64 functional, Z formation, E_xc/N_e
                                 sums and V accumulation */
 #define XC_MIXED_BF16X3  2   /* reserved: split-BF16 contractions with FP32 accumulate */
+#define XC_MIXED_FP32_V  3   /* FP64 collocation and density contraction, so E_xc, N_e
+                                and the functional inputs are as in XC_FP64; Z and the
+                                V^j contraction in FP32 (FP32 MFMA, FP32 accumulate),
+                                V accumulated in FP64 */
 
 /*
  * Atoms (Sec. 2.2, eq. atomic_partition): centres R_A in bohr (natoms x 3,

@@ -521,7 +521,7 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
         R.epart[B.batch] = es;
         R.npart[B.batch] = ns;
     }
-    T* Zm = (T*)(scratch + 8 * B.phi_off) + (size_t)B.nbp * B.ngp;
+    T* Zm = (T*)(scratch + 8 * (B.phi_off + (long long)B.nbp * B.ngp));
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) Zm[(size_t)B.nb * B.ngp + k] = T(0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -551,8 +551,9 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
 // ------------------------------------------------------ potential (SYR2K) --
 // Lower-triangle tile (I >= J) of V^j = Z Phi^T + Phi Z^T, 64 x 64, over all
 // points of the batch, added into V[f(row)][f(col)] (f ascending, so the
-// global entry is in the lower triangle too).
-template <typename T>
+// global entry is in the lower triangle too). T is the arithmetic (and the
+// storage of Z), TP the storage of Phi.
+template <typename T, typename TP>
 __global__ __launch_bounds__(256) void k_syr2k(
     const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
     int ntiles, const ReqDev* __restrict__ reqs, const char* __restrict__ scratch) {
@@ -570,8 +571,8 @@ __global__ __launch_bounds__(256) void k_syr2k(
     while (I * (I + 1) / 2 > lt) --I;
     const int J = lt - I * (I + 1) / 2;
     const size_t slab = (size_t)B.nbp * B.ngp;
-    const T* Phi = (const T*)(scratch + 8 * B.phi_off);
-    const T* Zm = Phi + slab;
+    const TP* Phi = (const TP*)(scratch + 8 * B.phi_off);
+    const T* Zm = (const T*)(scratch + 8 * (B.phi_off + (long long)slab));
     const gptr<const int> fl = func_list + B.func_off;
 
     // K steps of 8 keep the four double-buffered operand tiles at 37 KB of
@@ -598,9 +599,9 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const int rI = I * kTile + lr, rJ = J * kTile + lr;
     const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
     const T* zI = Zm + (size_t)(vI ? rI : 0) * B.ngp;
-    const T* pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
+    const TP* pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
     const T* zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
-    const T* pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
+    const TP* pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
 
     // FP32: loads from the clamped (always valid) rows, padding rows zeroed
     // after the load, so no branch separates the loads (with a branch around
@@ -610,18 +611,19 @@ __global__ __launch_bounds__(256) void k_syr2k(
     auto gload = [&](int ks) {
         const int k0 = ks * KS + lc;
         if constexpr (sizeof(T) == 4) {
+            TP ph[2][2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 g[0][q] = zI[k0 + q];
-                g[1][q] = pI[k0 + q];
-                g[2][q] = pJ[k0 + q];
+                ph[0][q] = pI[k0 + q];
+                ph[1][q] = pJ[k0 + q];
                 g[3][q] = zJ[k0 + q];
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 g[0][q] = vI ? g[0][q] : T(0);
-                g[1][q] = vI ? g[1][q] : T(0);
-                g[2][q] = vJ ? g[2][q] : T(0);
+                g[1][q] = vI ? T(ph[0][q]) : T(0);
+                g[2][q] = vJ ? T(ph[1][q]) : T(0);
                 g[3][q] = vJ ? g[3][q] : T(0);
             }
         } else {
@@ -762,7 +764,9 @@ __global__ void k_reduce_en(const double* epart, const double* npart, long long 
 }
 
 // ------------------------------------------------------------- driver -----
-template <bool GGA, typename T>
+// T: storage of Phi and arithmetic of the density contraction; TZ: storage
+// of Z and arithmetic of the potential contraction.
+template <bool GGA, typename T, typename TZ>
 static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                          const int* gpre, const int* spre, int count, int gemm_tiles,
                          int syr_tiles, const ReqDev* reqs, char* scr) {
@@ -779,12 +783,12 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
     }
     {
         PhaseScope ps(timer, s, XC_PHASE_FUNCTIONAL);
-        hipLaunchKernelGGL((k_func_z<GGA, T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        hipLaunchKernelGGL((k_func_z<GGA, TZ>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (syr_tiles > 0) {
         PhaseScope ps(timer, s, XC_PHASE_POTENTIAL);
-        hipLaunchKernelGGL((k_syr2k<T>), dim3(syr_tiles), dim3(256), 0, s, b, spre, count,
+        hipLaunchKernelGGL((k_syr2k<TZ, T>), dim3(syr_tiles), dim3(256), 0, s, b, spre, count,
                            syr_tiles, reqs, (const char*)scr);
         XC_HIP(hipGetLastError());
     }
@@ -796,14 +800,21 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch) {
     if (count == 0) return XC_OK;
     if (precision == XC_MIXED_FP32)
-        return gga ? launch_wave_t<true, float>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                gemm_tiles, syr_tiles, d_reqs, scratch)
-                   : launch_wave_t<false, float>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                 gemm_tiles, syr_tiles, d_reqs, scratch);
-    return gga ? launch_wave_t<true, double>(timer, s, d_wb, d_gpre, d_spre, count,
-                                             gemm_tiles, syr_tiles, d_reqs, scratch)
-               : launch_wave_t<false, double>(timer, s, d_wb, d_gpre, d_spre, count,
-                                              gemm_tiles, syr_tiles, d_reqs, scratch);
+        return gga ? launch_wave_t<true, float, float>(timer, s, d_wb, d_gpre, d_spre, count,
+                                                       gemm_tiles, syr_tiles, d_reqs, scratch)
+                   : launch_wave_t<false, float, float>(timer, s, d_wb, d_gpre, d_spre,
+                                                        count, gemm_tiles, syr_tiles, d_reqs,
+                                                        scratch);
+    if (precision == XC_MIXED_FP32_V)
+        return gga ? launch_wave_t<true, double, float>(timer, s, d_wb, d_gpre, d_spre, count,
+                                                        gemm_tiles, syr_tiles, d_reqs, scratch)
+                   : launch_wave_t<false, double, float>(timer, s, d_wb, d_gpre, d_spre,
+                                                         count, gemm_tiles, syr_tiles, d_reqs,
+                                                         scratch);
+    return gga ? launch_wave_t<true, double, double>(timer, s, d_wb, d_gpre, d_spre, count,
+                                                     gemm_tiles, syr_tiles, d_reqs, scratch)
+               : launch_wave_t<false, double, double>(timer, s, d_wb, d_gpre, d_spre, count,
+                                                      gemm_tiles, syr_tiles, d_reqs, scratch);
 }
 
 int launch_finish(PhaseTimer* timer, hipStream_t s, double* dV, int nbf,

@@ -68,6 +68,7 @@ def test_engine_mixed_precisions_and_oracle():
     from paper_2007_03143_amd.serving import serve
     reqs = _requests(n=4, n_iter=2)
     reqs[1].precision = "fp32"
+    reqs[2].precision = "fp32v"
     ref = [_alone(r) for r in reqs]
     serve(reqs, wave_bytes=8 << 20, keep_v=lambda i: True)
     for r, rr in zip(reqs, ref):

@@ -196,3 +196,22 @@ def test_mixed_fp32_error_vs_oracle(functional):
     assert abs(E - Eo) <= 1e-5 and abs(N - No) <= 1e-5
     assert np.abs(V - Vo).max() <= 1e-4
     assert np.array_equal(V, V.T)
+
+
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_mixed_fp32_potential_error_vs_oracle(functional):
+    """FP64 collocation and density contraction, FP32 Z and potential
+    contraction: E_xc and N_e equal the FP64 path's bit for bit (and so meet
+    the FP64 tolerance against the oracle); the V error is reported and
+    bounded."""
+    w = cfg_water()
+    say(f"case water {functional} fp32v")
+    from gpu_util import gpu_integrate_prec
+    E, N, V, st = gpu_integrate_prec(w, functional, "fp32v")
+    E64, N64, V64, _ = gpu_integrate_prec(w, functional, "fp64")
+    Eo, No, Vo = oracle_integrate(w, functional)
+    say(f"  fp32v: dE {E - Eo:.3e} dN {N - No:.3e} max dV {np.abs(V - Vo).max():.3e}")
+    assert E == E64 and N == N64
+    assert abs(E - Eo) <= TOL_E and abs(N - No) <= TOL_E
+    assert np.abs(V - Vo).max() <= 1e-4
+    assert np.array_equal(V, V.T)

@@ -30,6 +30,36 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+# phase -> (kernel, source file)
+PHASE_KERNEL = {"density": ("k_gemm_rho", "paper_2007_03143_amd/csrc/integrate.hip"),
+                "potential": ("k_syr2k", "paper_2007_03143_amd/csrc/integrate.hip")}
+
+
+def source_sha256(rel):
+    import hashlib
+    with open(os.path.join(HERE, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def profiled_traffic(kernel, workload, sha):
+    """HBM bytes per launch of `kernel` on `workload` from the counter
+    summaries under profiles/ (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
+    a plain copy of known size), used only if they were taken on this exact
+    kernel source; otherwise (None, None)."""
+    import glob
+    import re
+    pat = re.compile(r"^traffic: kernel=(\S+) workload=(\S+) source_sha256=(\S+) "
+                     r"fetch_bytes_per_launch=(\d+) write_bytes_per_launch=(\d+)")
+    for path in sorted(glob.glob(os.path.join(HERE, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                m = pat.match(line.strip())
+                if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == sha:
+                    return int(m.group(4)) + int(m.group(5)), os.path.relpath(path, HERE)
+    return None, None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -226,13 +256,21 @@ def main():
              "potential": 2.0 * (st["sum_nb2_ng"] + st["sum_nb_ng"])}
     phase_ms = {k: v["ms"] / args.steps for k, v in timing.items()}
     dom = max(phase_ms, key=phase_ms.get)
+    workload_key = f"{w.name}_{functional}_{w.n_rad}x{w.n_ang}_fp64"
     if dom in flops:
+        launches = timing[dom]["launches"] / args.steps
         achieved = flops[dom] / (phase_ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": dom, "achieved": achieved,
+        kname, ksrc = PHASE_KERNEL[dom]
+        sha = source_sha256(ksrc)
+        traffic, tsrc = profiled_traffic(kname, workload_key, sha) if launches == 1 else (None, None)
+        roof = {"bound": "mfma", "kernel": kname, "phase": dom, "achieved": achieved,
                 "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
-                "flops_per_step": flops[dom],
-                "launches_per_step": timing[dom]["launches"] / args.steps}
+                "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch",
+                "traffic_source": tsrc, "kernel_source_sha256": sha,
+                "flops_per_launch": flops[dom] / launches if launches else None,
+                "ms_per_launch": phase_ms[dom] / launches if launches else None,
+                "launches_per_step": launches}
     else:
         roof = {"bound": "alu", "kernel": dom, "achieved": None,
                 "peak": None, "unit": None, "frac": None, "traffic": None}

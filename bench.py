@@ -150,7 +150,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="water64")
     ap.add_argument("--wave-gb", type=float, default=0.0)
-    ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-merge", type=int, default=1)
     ap.add_argument("--mixed", default="fp32,fp32v")

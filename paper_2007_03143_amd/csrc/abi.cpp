@@ -123,8 +123,8 @@ size_t device_bytes(const xc_context* c) {
                             &c->child_count, &c->child_begin, &c->batches, &c->counters,
                             &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
-                            &c->d_gemm_pre, &c->d_syr_pre, &c->scratch, &c->epart,
-                            &c->npart, &c->d_req};
+                            &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch,
+                            &c->epart, &c->npart, &c->d_req};
     size_t n = 0;
     for (const DevBuf* b : bufs) n += b->cap;
     return n;
@@ -217,8 +217,8 @@ static void release_all(xc_context* c) {
                       &c->child_count, &c->child_begin, &c->batches, &c->counters,
                       &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                       &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
-                      &c->d_gemm_pre, &c->d_syr_pre, &c->scratch, &c->epart, &c->npart,
-                      &c->d_req};
+                      &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch, &c->epart,
+                      &c->npart, &c->d_req};
     for (DevBuf* b : bufs) dev_release(*b);
 }
 
@@ -301,6 +301,9 @@ static int plan_waves(xc_context* c) {
                   c->stream));
     XC_TRY(upload(c->d_gemm_pre, gpre.data(), sizeof(int) * gpre.size(), c->stream));
     XC_TRY(upload(c->d_syr_pre, spre.data(), sizeof(int) * spre.size(), c->stream));
+    int max_tiles = 1;
+    for (const Wave& w : c->waves) max_tiles = std::max({max_tiles, w.gemm_tiles, w.syr_tiles});
+    XC_TRY(dev_reserve(c->d_tmap, 2 * sizeof(int) * (size_t)max_tiles));
     if (!c->external_scratch)
         XC_TRY(dev_reserve(c->scratch, std::max<size_t>(c->max_wave_bytes, 8)));
     XC_TRY(dev_reserve(c->epart, 8 * (size_t)std::max<long long>(1, c->n_batches)));
@@ -492,7 +495,8 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
                             &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
                             &c->d_fshell, &c->d_flmn, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
-                            &c->d_gemm_pre, &c->d_syr_pre, &c->epart, &c->npart};
+                            &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->epart,
+                            &c->npart};
     for (const DevBuf* b : bufs) pers += b->cap;
     s->persistent_bytes = pers;
     s->wave_bytes = c->max_wave_bytes;

@@ -67,21 +67,31 @@ __device__ inline int cell_coord(double v, double lo, double ext, int ns) {
     return t < 0 ? 0 : (t >= ns ? ns - 1 : t);
 }
 
-// One workgroup (kSplitThreads threads) splits one cell. Thread t owns a
-// contiguous chunk of the cell's points; per-thread child counts and a scan
-// over (child, thread) give every point its stable destination.
+// One workgroup (kSplitThreads threads) splits one cell into its 27 or 8
+// children, stably (points keep their order within each child). The cell's
+// points are taken in rounds of kSplitThreads consecutive points, one per
+// thread, so every load is coalesced. A first pass counts the children with
+// LDS atomics; the second gives each point its rank among the round's points
+// of the same child (ballots within the wave, a prefix over the waves) and
+// writes it to its child's range of the scratch arrays, which are then
+// copied back.
 constexpr int kSplitThreads = 1024;
+constexpr int kSplitWaves = kSplitThreads / 64;
 
 __global__ __launch_bounds__(kSplitThreads) void k_split(
     const Cell* cells, const double4* atoms, int natoms, double* X, double* Y,
     double* Z, double* W, long long* I, double* TX, double* TY, double* TZ,
     double* TW, long long* TI, int* child_count, long long* child_begin) {
     const Cell c = cells[blockIdx.x];
-    __shared__ int cnt[kSplitThreads][kMaxChild + 1];
-    __shared__ int tot[kMaxChild + 1], base[kMaxChild + 1];
+    __shared__ int wcnt[kSplitWaves][kMaxChild];
+    __shared__ int tot[kMaxChild], base[kMaxChild], run[kMaxChild];
     __shared__ int has_centre;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) has_centre = 0;
+    if (tid < kMaxChild) {
+        tot[tid] = 0;
+        run[tid] = 0;
+    }
     __syncthreads();
     for (int a = tid; a < natoms; a += blockDim.x) {
         const double4 r = atoms[a];
@@ -94,25 +104,13 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(
     const int nchild = ns * ns * ns;
     const double ex = c.hi[0] - c.lo[0], ey = c.hi[1] - c.lo[1], ez = c.hi[2] - c.lo[2];
     const int n = c.count;
-    const int chunk = (n + kSplitThreads - 1) / kSplitThreads;
-    const int s0 = min(n, tid * chunk), s1 = min(n, s0 + chunk);
-    for (int k = 0; k < kMaxChild; ++k) cnt[tid][k] = 0;
-    for (int j = s0; j < s1; ++j) {
+    auto child = [&](double x, double y, double z) {
+        return (cell_coord(x, c.lo[0], ex, ns) * ns + cell_coord(y, c.lo[1], ey, ns)) * ns +
+               cell_coord(z, c.lo[2], ez, ns);
+    };
+    for (int j = tid; j < n; j += kSplitThreads) {
         const long long p = c.begin + j;
-        const int k = (cell_coord(X[p], c.lo[0], ex, ns) * ns +
-                       cell_coord(Y[p], c.lo[1], ey, ns)) * ns +
-                      cell_coord(Z[p], c.lo[2], ez, ns);
-        cnt[tid][k]++;
-    }
-    __syncthreads();
-    if (tid < nchild) {
-        int run = 0;
-        for (int t = 0; t < kSplitThreads; ++t) {
-            const int v = cnt[t][tid];
-            cnt[t][tid] = run;
-            run += v;
-        }
-        tot[tid] = run;
+        atomicAdd(&tot[child(X[p], Y[p], Z[p])], 1);
     }
     __syncthreads();
     if (tid == 0) {
@@ -123,19 +121,46 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(
         }
     }
     __syncthreads();
-    for (int j = s0; j < s1; ++j) {
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r0 = 0; r0 < n; r0 += kSplitThreads) {
+        const int j = r0 + tid;
+        const bool v = j < n;
         const long long p = c.begin + j;
-        const int k = (cell_coord(X[p], c.lo[0], ex, ns) * ns +
-                       cell_coord(Y[p], c.lo[1], ey, ns)) * ns +
-                      cell_coord(Z[p], c.lo[2], ez, ns);
-        const long long d = c.begin + base[k] + cnt[tid][k]++;
-        TX[d] = X[p];
-        TY[d] = Y[p];
-        TZ[d] = Z[p];
-        TW[d] = W[p];
-        TI[d] = I[p];
+        double x = 0.0, y = 0.0, z = 0.0;
+        int k = -1;
+        if (v) {
+            x = X[p];
+            y = Y[p];
+            z = Z[p];
+            k = child(x, y, z);
+        }
+        int rank = 0;
+        for (int kk = 0; kk < nchild; ++kk) {
+            const unsigned long long m = __ballot(k == kk);
+            if (k == kk) rank = __popcll(m & below);
+            if (lane == 0) wcnt[wv][kk] = __popcll(m);
+        }
+        __syncthreads();
+        if (tid < nchild) {
+            int s = run[tid];
+            for (int w = 0; w < kSplitWaves; ++w) {
+                const int t = wcnt[w][tid];
+                wcnt[w][tid] = s;
+                s += t;
+            }
+            run[tid] = s;
+        }
+        __syncthreads();
+        if (v) {
+            const long long d = c.begin + base[k] + wcnt[wv][k] + rank;
+            TX[d] = x;
+            TY[d] = y;
+            TZ[d] = z;
+            TW[d] = W[p];
+            TI[d] = I[p];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int j = tid; j < n; j += blockDim.x) {
         const long long p = c.begin + j;
         X[p] = TX[p];

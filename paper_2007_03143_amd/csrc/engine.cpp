@@ -49,7 +49,7 @@ struct xc_engine {
     size_t budget = 0;
     size_t wave_bytes = 0;
     size_t used = 0;
-    xc::DevBuf scratch, d_wb, d_gpre, d_spre, d_reqs;
+    xc::DevBuf scratch, d_wb, d_gpre, d_spre, d_reqs, d_tmap;
     std::map<long long, xc::Request*> reqs;
     std::deque<long long> waiting;
     std::map<long long, xc::Integration*> tickets;
@@ -205,10 +205,13 @@ static int engine_step(xc_engine* e, int* launched) {
     if (!all_wb.empty()) {
         // growing a descriptor buffer frees the old one: let earlier steps that
         // read it finish first
-        const size_t need[4] = {sizeof(WaveBatch) * all_wb.size(), sizeof(int) * all_g.size(),
-                                sizeof(int) * all_s.size(), sizeof(ReqDev) * all_rd.size()};
-        const DevBuf* bufs[4] = {&e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs};
-        for (int q = 0; q < 4; ++q) {
+        int max_tiles = 1;
+        for (const auto& kv : groups) max_tiles = std::max({max_tiles, kv.second.gemm, kv.second.syr});
+        const size_t need[5] = {sizeof(WaveBatch) * all_wb.size(), sizeof(int) * all_g.size(),
+                                sizeof(int) * all_s.size(), sizeof(ReqDev) * all_rd.size(),
+                                2 * sizeof(int) * (size_t)max_tiles};
+        const DevBuf* bufs[5] = {&e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs, &e->d_tmap};
+        for (int q = 0; q < 5; ++q) {
             if (bufs[q]->cap < need[q]) {
                 XC_HIP(hipStreamSynchronize(e->stream));
                 break;
@@ -218,6 +221,7 @@ static int engine_step(xc_engine* e, int* launched) {
         XC_TRY(dev_reserve(e->d_gpre, 2 * need[1]));
         XC_TRY(dev_reserve(e->d_spre, 2 * need[2]));
         XC_TRY(dev_reserve(e->d_reqs, 2 * need[3]));
+        XC_TRY(dev_reserve(e->d_tmap, 2 * need[4]));
         XC_TRY(upload(e->d_wb, all_wb.data(), sizeof(WaveBatch) * all_wb.size(), e->stream));
         XC_TRY(upload(e->d_gpre, all_g.data(), sizeof(int) * all_g.size(), e->stream));
         XC_TRY(upload(e->d_spre, all_s.data(), sizeof(int) * all_s.size(), e->stream));
@@ -231,7 +235,8 @@ static int engine_step(xc_engine* e, int* launched) {
                                (const WaveBatch*)e->d_wb.p + o.wb,
                                (const int*)e->d_gpre.p + o.pre,
                                (const int*)e->d_spre.p + o.pre, (int)g.wb.size(), g.gemm,
-                               g.syr, (const ReqDev*)e->d_reqs.p, (char*)e->scratch.p));
+                               g.syr, (const ReqDev*)e->d_reqs.p, (char*)e->scratch.p,
+                               (int*)e->d_tmap.p));
         }
         e->batches_launched += *launched;
     }
@@ -399,7 +404,7 @@ int xc_engine_destroy(xc_engine* e) {
         destroy_request(e, kv.second);
         delete kv.second;
     }
-    DevBuf* bufs[] = {&e->scratch, &e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs};
+    DevBuf* bufs[] = {&e->scratch, &e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs, &e->d_tmap};
     for (DevBuf* b : bufs) dev_release(*b);
     delete e;
     return XC_OK;

@@ -304,10 +304,61 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
 // not zero; every other P_C is exactly zero.
 constexpr int kSsfWaveMaxAtoms = 1024;
 
+// Wave reductions without the LDS unit: DPP moves inside each 16-lane row
+// (swap neighbours, swap pairs, mirror the half-rows, mirror the rows), then
+// the four row results are read into scalar registers. Every lane ends with
+// the same value.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL>((int)b);
+    const int hi = dpp_i32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppMirror = 0x140;     // row_mirror
+
 __device__ inline double wave_product(double v) {
+    v *= dpp_f64<kDppXor1>(v);
+    v *= dpp_f64<kDppXor2>(v);
+    v *= dpp_f64<kDppHalfMirror>(v);
+    v *= dpp_f64<kDppMirror>(v);
+    return (readlane_f64(v, 0) * readlane_f64(v, 16)) *
+           (readlane_f64(v, 32) * readlane_f64(v, 48));
+}
+
+__device__ inline void argmin_take(double& d, int& b, double od, int ob) {
+    if (od < d || (od == d && ob < b)) {
+        d = od;
+        b = ob;
+    }
+}
+
+// smallest d over the wave, ties to the smaller index b
+__device__ inline void wave_argmin(double& d, int& b) {
+    argmin_take(d, b, dpp_f64<kDppXor1>(d), dpp_i32<kDppXor1>(b));
+    argmin_take(d, b, dpp_f64<kDppXor2>(d), dpp_i32<kDppXor2>(b));
+    argmin_take(d, b, dpp_f64<kDppHalfMirror>(d), dpp_i32<kDppHalfMirror>(b));
+    argmin_take(d, b, dpp_f64<kDppMirror>(d), dpp_i32<kDppMirror>(b));
+    double rd = readlane_f64(d, 0);
+    int rb = __builtin_amdgcn_readlane(b, 0);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
-    return v;
+    for (int r = 16; r < 64; r += 16)
+        argmin_take(rd, rb, readlane_f64(d, r), __builtin_amdgcn_readlane(b, r));
+    d = rd;
+    b = rb;
 }
 
 template <int NPER>
@@ -339,8 +390,8 @@ __global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const in
     while (todo) {
         const int l = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
-        const double px = __shfl(x, l, 64), py = __shfl(y, l, 64), pz = __shfl(z, l, 64);
-        const int pA = __shfl(A, l, 64);
+        const double px = readlane_f64(x, l), py = readlane_f64(y, l), pz = readlane_f64(z, l);
+        const int pA = __builtin_amdgcn_readlane(A, l);
         // this lane's atoms: distances, and the nearest atom over the wave
         double d[NPER];
         double dmin = INFINITY;
@@ -354,15 +405,7 @@ __global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const in
                 bmin = B;
             }
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double od = __shfl_xor(dmin, o, 64);
-            const int ob = __shfl_xor(bmin, o, 64);
-            if (od < dmin || (od == dmin && ob < bmin)) {
-                dmin = od;
-                bmin = ob;
-            }
-        }
+        wave_argmin(dmin, bmin);
         // P_C = prod_{B != C} s(mu_CB), spread over the lanes
         auto cell = [&](int C) {
             const double dC = sqrt(dist2_to(sat[C], px, py, pz));

@@ -238,17 +238,18 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
 // part[mt][q][point], q = rho, dx, dy, dz.
 template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_gemm_rho(
-    const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
-    int ntiles, const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
+    const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
+    const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
     using M = Mfma<T>;
     const int t = xcd_remap(blockIdx.x, ntiles);
-    const int bi = find_segment(prefix, nwb, t);
+    const int2 tb = tmap[t];
+    const int bi = tb.x;
     const WaveBatch B = wb[bi];
     const ReqG R = global_view(reqs[B.req]);
     const gptr<const double> P = R.P;
     const int nbf = R.nbf;
     const gptr<const int> func_list = R.func_list;
-    const int lt = t - prefix[bi];
+    const int lt = tb.y;
     const int ntn = B.ngp / kTile;
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
@@ -555,17 +556,18 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
 // storage of Z), TP the storage of Phi.
 template <typename T, typename TP>
 __global__ __launch_bounds__(256) void k_syr2k(
-    const WaveBatch* __restrict__ wb, const int* __restrict__ prefix, int nwb,
-    int ntiles, const ReqDev* __restrict__ reqs, const char* __restrict__ scratch) {
+    const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
+    const ReqDev* __restrict__ reqs, const char* __restrict__ scratch) {
     using M = Mfma<T>;
     const int t = xcd_remap(blockIdx.x, ntiles);
-    const int bi = find_segment(prefix, nwb, t);
+    const int2 tb = tmap[t];
+    const int bi = tb.x;
     const WaveBatch B = wb[bi];
     const ReqG R = global_view(reqs[B.req]);
     const gptr<const int> func_list = R.func_list;
     const gptr<double> V = R.V;
     const int nbf = R.nbf;
-    const int lt = t - prefix[bi];
+    const int lt = tb.y;
     int I = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= lt) ++I;
     while (I * (I + 1) / 2 > lt) --I;
@@ -718,6 +720,15 @@ __global__ __launch_bounds__(256) void k_syr2k(
 }
 
 // ---------------------------------------------------------------- misc ----
+// Tile -> (batch, tile within the batch) for one launch over nwb batches whose
+// tile counts have the exclusive prefix `prefix`: one thread per batch.
+__global__ void k_tile_map(const int* __restrict__ prefix, int nwb, int2* __restrict__ map) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nwb) return;
+    const int t0 = prefix[b], t1 = prefix[b + 1];
+    for (int t = t0; t < t1; ++t) map[t] = make_int2(b, t - t0);
+}
+
 __global__ void k_fill(double* p, long long n, double v) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -769,7 +780,7 @@ __global__ void k_reduce_en(const double* epart, const double* npart, long long 
 template <bool GGA, typename T, typename TZ>
 static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                          const int* gpre, const int* spre, int count, int gemm_tiles,
-                         int syr_tiles, const ReqDev* reqs, char* scr) {
+                         int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap) {
     {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
         hipLaunchKernelGGL((k_colloc<T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
@@ -777,8 +788,11 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
     }
     if (gemm_tiles > 0) {
         PhaseScope ps(timer, s, XC_PHASE_DENSITY);
-        hipLaunchKernelGGL((k_gemm_rho<GGA, T>), dim3(gemm_tiles), dim3(256), 0, s, b, gpre,
-                           count, gemm_tiles, reqs, scr);
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, gpre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_gemm_rho<GGA, T>), dim3(gemm_tiles), dim3(256), 0, s, b,
+                           (const int2*)tmap, gemm_tiles, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     {
@@ -788,8 +802,11 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
     }
     if (syr_tiles > 0) {
         PhaseScope ps(timer, s, XC_PHASE_POTENTIAL);
-        hipLaunchKernelGGL((k_syr2k<TZ, T>), dim3(syr_tiles), dim3(256), 0, s, b, spre, count,
-                           syr_tiles, reqs, (const char*)scr);
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, spre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_syr2k<TZ, T>), dim3(syr_tiles), dim3(256), 0, s, b,
+                           (const int2*)tmap, syr_tiles, reqs, (const char*)scr);
         XC_HIP(hipGetLastError());
     }
     return XC_OK;
@@ -797,24 +814,26 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
 
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre, int count,
-                int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch) {
+                int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch,
+                int* d_tmap_i) {
     if (count == 0) return XC_OK;
+    int2* d_tmap = (int2*)d_tmap_i;
     if (precision == XC_MIXED_FP32)
         return gga ? launch_wave_t<true, float, float>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                       gemm_tiles, syr_tiles, d_reqs, scratch)
+                                                       gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap)
                    : launch_wave_t<false, float, float>(timer, s, d_wb, d_gpre, d_spre,
                                                         count, gemm_tiles, syr_tiles, d_reqs,
-                                                        scratch);
+                                                        scratch, d_tmap);
     if (precision == XC_MIXED_FP32_V)
         return gga ? launch_wave_t<true, double, float>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                        gemm_tiles, syr_tiles, d_reqs, scratch)
+                                                        gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap)
                    : launch_wave_t<false, double, float>(timer, s, d_wb, d_gpre, d_spre,
                                                          count, gemm_tiles, syr_tiles, d_reqs,
-                                                         scratch);
+                                                         scratch, d_tmap);
     return gga ? launch_wave_t<true, double, double>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                     gemm_tiles, syr_tiles, d_reqs, scratch)
+                                                     gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap)
                : launch_wave_t<false, double, double>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                      gemm_tiles, syr_tiles, d_reqs, scratch);
+                                                      gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap);
 }
 
 int launch_finish(PhaseTimer* timer, hipStream_t s, double* dV, int nbf,
@@ -879,7 +898,8 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
     for (const Wave& w : c->waves)
         XC_TRY(launch_wave(&c->timer, c->stream, gga, precision, wb + w.wb_off,
                            gpre + w.pre_off, spre + w.pre_off, w.count, w.gemm_tiles,
-                           w.syr_tiles, (const ReqDev*)c->d_req.p, (char*)c->scratch.p));
+                           w.syr_tiles, (const ReqDev*)c->d_req.p, (char*)c->scratch.p,
+                           (int*)c->d_tmap.p));
     return launch_finish(&c->timer, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);
 }

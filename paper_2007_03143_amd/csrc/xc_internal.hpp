@@ -175,6 +175,7 @@ struct xc_context {
     std::vector<xc::Wave> waves;
     std::vector<xc::WaveBatch> h_wb;
     xc::DevBuf d_wb, d_gemm_pre, d_syr_pre;
+    xc::DevBuf d_tmap;           // tile -> (batch, tile in batch) of one launch
     xc::DevBuf scratch;
     size_t max_wave_bytes = 0;
     xc::DevBuf epart, npart;
@@ -232,10 +233,11 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
 ReqDev make_req(const xc_context* c, const double* dP, double* dV);
 // The four per-wave launches (collocation, density, functional + Z,
 // potential) over count batches whose descriptors are already on the device.
+// d_tmap: room for 2 * max(gemm_tiles, syr_tiles) ints (tile -> batch map).
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre,
                 int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
-                char* scratch);
+                char* scratch, int* d_tmap);
 // Fill n doubles with v (a kernel, so it can be captured in a graph).
 int launch_fill(hipStream_t s, double* p, long long n, double v);
 // V mirror and the fixed-order E_xc / N_e sums of one finished integration.

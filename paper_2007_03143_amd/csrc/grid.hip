@@ -330,6 +330,15 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 constexpr int kDppMirror = 0x140;     // row_mirror
 
+// s(mu) with z = mu (1/a): a multiplication in place of the division
+__device__ inline double ssf_s_inv(double mu, double a, double inv_a) {
+    if (mu <= -a) return 1.0;
+    if (mu >= a) return 0.0;
+    const double z = mu * inv_a, z2 = z * z;
+    const double g = z * (35.0 + z2 * (-35.0 + z2 * (21.0 - 5.0 * z2))) * 0.0625;
+    return 0.5 * (1.0 - g);
+}
+
 __device__ inline double wave_product(double v) {
     v *= dpp_f64<kDppXor1>(v);
     v *= dpp_f64<kDppXor2>(v);
@@ -386,6 +395,7 @@ __global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const in
         }
     }
     const double far = (1.0 + a) / (1.0 - a) * (1.0 + 1e-12);
+    const double inv_a = 1.0 / a;
     unsigned long long todo = __ballot(need);
     while (todo) {
         const int l = __ffsll((unsigned long long)todo) - 1;
@@ -414,7 +424,7 @@ __global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const in
 #pragma unroll
             for (int j = 0; j < NPER; ++j) {
                 const int B = lane + 64 * j;
-                if (B < natoms && B != C) p *= ssf_s((dC - d[j]) * ir[B], a);
+                if (B < natoms && B != C) p *= ssf_s_inv((dC - d[j]) * ir[B], a, inv_a);
             }
             return wave_product(p);
         };

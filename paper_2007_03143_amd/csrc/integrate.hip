@@ -115,6 +115,30 @@ __device__ inline void shell_radial(const ShellDev& sh, gptr<const double> palph
     }
 }
 
+// The same for a shell that is the same on every lane of the wave, with a
+// primitive skipped when alpha r2 >= 746 on every lane: its exponential is
+// then exactly zero in FP64 everywhere, so the sums are the same bit for bit
+// (tight primitives far from their centre, the common case in the density
+// epilogue), and the wave-wide test keeps the lanes together.
+constexpr double kExpZero = 746.0;
+
+__device__ inline void shell_radial_wave(const ShellDev& sh, gptr<const double> palpha,
+                                         gptr<const double> pcoef, double r2, double& rad,
+                                         double& drad) {
+    rad = 0.0;
+    drad = 0.0;
+    const bool in = r2 <= sh.rcut2;
+    for (int p = 0; p < sh.nprim; ++p) {
+        const double a = palpha[sh.prim_off + p];
+        const double x = a * r2;
+        if (__any(in && x < kExpZero)) {
+            const double de = in ? pcoef[sh.prim_off + p] * exp(-x) : 0.0;
+            rad += de;
+            drad -= 2.0 * a * de;
+        }
+    }
+}
+
 // Squared distance with the same rounding in every kernel (no contraction),
 // so the cutoff test gives the same answer wherever it is evaluated.
 __device__ inline double dist2_nc(double x, double y, double z, const ShellDev& sh,
@@ -416,11 +440,12 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         for (int rr = 0; rr < 16; ++rr) {
             const int rl = g * 16 + rr;
             if (m0 + rl >= B.nb) break;
-            const int sidx = fsh[rl];
+            // one row group per wave: the shell is wave-uniform
+            const int sidx = __builtin_amdgcn_readfirstlane(fsh[rl]);
             if (sidx != prev) {
                 const ShellDev sh = load_shell(R.shells + sidx);
                 const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
-                shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
+                shell_radial_wave(sh, R.palpha, R.pcoef, r2, rad, drad);
                 prev = sidx;
             }
             const int lmn = flmn[rl];

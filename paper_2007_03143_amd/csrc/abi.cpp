@@ -429,7 +429,7 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
     if (rc == XC_OK) rc = upload(c->d_atoms, c->atoms4.data(), 8 * c->atoms4.size(), c->stream);
     if (rc == XC_OK) rc = dev_reserve(c->d_invR, 8 * (size_t)c->natoms * c->natoms);
     if (rc == XC_OK) rc = dev_reserve(c->d_nnhalf, 8 * (size_t)c->natoms);
-    if (rc == XC_OK && c->natoms <= kNbrMaxAtoms) {
+    if (rc == XC_OK && c->natoms > kSsfWaveMaxAtoms && c->natoms <= kNbrMaxAtoms) {
         rc = dev_reserve(c->d_nbr_idx, sizeof(int) * (size_t)c->natoms * c->natoms);
         if (rc == XC_OK) rc = dev_reserve(c->d_nbr_R, 8 * (size_t)c->natoms * c->natoms);
     }

@@ -87,7 +87,7 @@ int launch_shell_setup(xc_context* c) {
                        c->stream, (const double4*)c->d_atoms.p, c->natoms, c->ssf_a,
                        (double*)c->d_invR.p, (double*)c->d_nnhalf.p);
     XC_HIP(hipGetLastError());
-    if (c->natoms <= kNbrMaxAtoms) {
+    if (c->natoms > kSsfWaveMaxAtoms && c->natoms <= kNbrMaxAtoms) {
         hipLaunchKernelGGL(k_atom_neighbours, dim3(c->natoms), dim3(256),
                            sizeof(double) * (size_t)c->natoms, c->stream,
                            (const double4*)c->d_atoms.p, c->natoms, (int*)c->d_nbr_idx.p,
@@ -200,25 +200,16 @@ __device__ inline double ssf_product_all(int C, double dC, const double4* atoms,
 //  * an atom C with (d_C - d_min) / R_{C,nearest} >= a has s(mu_{C,nearest}) = 0,
 //    hence P_C = 0, and is skipped;
 //  * inside a product only nearby atoms can differ from 1 (see above).
-// Atom centres are staged in LDS (dynamic size, up to kSsfLdsAtoms so
-// several workgroups still fit on a CU) and read by every lane together;
-// larger molecules read them from global memory. The two cases are separate
-// instantiations so that every access has a known address space.
-constexpr int kSsfLdsAtoms = 512;
-
-template <bool kInLds>
+// One lane per point; used for molecules with more atoms than the
+// one-wave-per-point kernel below takes, so the atom centres are read from
+// global memory.
 __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* gatoms,
                                              const double4* atoms_g, const double* invR,
                                              const int* nbr_idx, const double* nbr_R,
                                              const double* nnhalf, int natoms, double a,
                                              const double* X, const double* Y,
                                              const double* Z, double* W) {
-    extern __shared__ double4 sat[];
-    if (kInLds) {
-        for (int k = threadIdx.x; k < natoms; k += blockDim.x) sat[k] = atoms_g[k];
-        __syncthreads();
-    }
-    const double4* atoms = kInLds ? sat : atoms_g;
+    const double4* atoms = atoms_g;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double w = W[i];
@@ -302,7 +293,6 @@ __global__ __launch_bounds__(256) void k_ssf(long long n, int npa, const int* ga
 // by a butterfly over the wave. The atoms C that can share a point are those
 // with d_C < d_min (1 + a)/(1 - a) whose factor against the nearest atom is
 // not zero; every other P_C is exactly zero.
-constexpr int kSsfWaveMaxAtoms = 1024;
 
 // Wave reductions without the LDS unit: DPP moves inside each 16-lane row
 // (swap neighbours, swap pairs, mirror the half-rows, mirror the rows), then
@@ -469,10 +459,7 @@ int launch_ssf(xc_context* c) {
         XC_HIP(hipGetLastError());
         return XC_OK;
     }
-    const bool in_lds = c->natoms <= kSsfLdsAtoms;
-    const size_t lds = in_lds ? sizeof(double4) * (size_t)c->natoms : 0;
-    hipLaunchKernelGGL(in_lds ? k_ssf<true> : k_ssf<false>, dim3(grid_1d(c->n_nominal, 256)),
-                       dim3(256), lds, c->stream,
+    hipLaunchKernelGGL(k_ssf, dim3(grid_1d(c->n_nominal, 256)), dim3(256), 0, c->stream,
                        c->n_nominal, npa, (const int*)c->d_gatoms.p,
                        (const double4*)c->d_atoms.p, (const double*)c->d_invR.p,
                        c->natoms <= kNbrMaxAtoms ? (const int*)c->d_nbr_idx.p : nullptr,

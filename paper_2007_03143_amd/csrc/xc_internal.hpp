@@ -38,7 +38,8 @@ constexpr int kMaxBatch = 1024;     // largest batch_max accepted
 constexpr int kTile = 64;           // contraction tile edge (rows and columns)
 constexpr int kRowPad = 16;         // n_b is stored padded to a multiple of this
 constexpr int kColPad = 64;         // n_g is stored padded to a multiple of this
-constexpr int kNbrMaxAtoms = 4096;  // distance-ordered neighbour lists up to this many atoms
+constexpr int kSsfWaveMaxAtoms = 1024;  // partition with one wave per point up to this many atoms
+constexpr int kNbrMaxAtoms = 4096;  // beyond that, distance-ordered neighbour lists up to this many
 
 // One basis shell as the kernels read it.
 struct ShellDev {

@@ -119,6 +119,44 @@ def test_grid_points_and_weights_match_oracle():
     assert np.all(wo[dropped] <= 1e-13 * wq[dropped])
 
 
+@pytest.mark.parametrize("n_waters,n_rad,n_ang", [(400, 6, 14), (1400, 4, 6)])
+def test_large_molecule_weights_match_oracle(n_waters, n_rad, n_ang):
+    """Partition weights of molecules past the one-wave-per-point limit:
+    1200 atoms (distance-ordered neighbour lists) and 4200 atoms (all-pairs
+    products). The grids of two parent atoms (an O and an H) are built; the
+    partition runs over every atom on both sides."""
+    from paper_2007_03143_amd import XcContext
+    from workloads.molecules import water_cluster
+    from workloads.angular import lebedev_table
+    from workloads.configs import MK_ALPHA
+    mol = water_cluster(n_waters, box=25.0 * (n_waters / 64.0) ** (1.0 / 3.0), seed=11)
+    basis = make_basis(mol.Z)
+    mk = np.array([MK_ALPHA[int(z)] for z in mol.Z])
+    ang = lebedev_table(n_ang)
+    mask = np.zeros(mol.natoms, np.uint8)
+    mask[[0, 3 * (n_waters // 2) + 1]] = 1
+    say(f"case weights {mol.natoms} atoms, {n_rad} x {n_ang}")
+    grid = dict(n_rad=n_rad, n_ang=n_ang, ang=ang, ssf_a=0.64, screen_eta=1e-10,
+                batch_max=512, rho_thresh=1e-15, atom_mask=mask)
+    ctx = XcContext(mol.coords, mk, basis, grid)
+    try:
+        ctx.build_grid()
+        xyzw, idx = ctx.export_grid()
+    finally:
+        ctx.close()
+    pts, wq, par = oracle.molecular_grid(mol.coords, mk, n_rad, ang, atom_mask=mask)
+    wo = oracle.ssf_weights(pts, wq, par, mol.coords)
+    assert len(np.unique(idx)) == len(idx)
+    assert np.abs(xyzw[:, :3] - pts[idx]).max() <= 1e-13 * np.abs(pts).max()
+    full = np.zeros_like(wo)
+    full[idx] = xyzw[:, 3]
+    say(f"  kept {len(idx)} of {len(wo)} points, max |dw|/w_q "
+        f"{np.max(np.abs(full - wo) / wq):.2e}")
+    assert np.all(np.abs(full - wo) <= 1e-13 * wq)
+    dropped = np.setdiff1d(np.arange(len(wo)), idx)
+    assert np.all(wo[dropped] <= 1e-13 * wq[dropped])
+
+
 @pytest.mark.parametrize("name", ["water", "cluster8"])
 def test_batches_and_screening_lists(name):
     w = cfg_water() if name == "water" else cfg_water_cluster(8, functional="pbe",

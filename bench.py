@@ -172,8 +172,9 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU's share only; runs on more than one GPU "
-              "are not part of this build (see the sharding design).", file=sys.stderr)
+        print("bench.py measures one GPU's share only; runs on more than one GPU are "
+              "not supported (the sharding across GPUs is a design, not an implementation).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

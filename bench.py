@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-merge", type=int, default=1)
-    ap.add_argument("--mixed", default="fp32,fp32v")
+    ap.add_argument("--mixed", default="fp32,fp32v,bf16x3")
     ap.add_argument("--serving", type=int, default=40,
                     help="requests in the serving stream (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

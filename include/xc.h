@@ -58,7 +58,10 @@ extern "C" {
 #define XC_MIXED_FP32    1   /* FP32 collocation and contractions (FP32 MFMA, FP32
                                 accumulate); FP64 functional, Z formation, E_xc/N_e
                                 sums and V accumulation */
-#define XC_MIXED_BF16X3  2   /* reserved: split-BF16 contractions with FP32 accumulate */
+#define XC_MIXED_BF16X3  2   /* Phi and Z stored in FP32; both contractions in split
+                                BF16 (x = hi + lo, products hi hi + hi lo + lo hi on
+                                BF16 MFMA, FP32 accumulate); FP64 functional, Z
+                                formation, E_xc/N_e sums and V accumulation */
 #define XC_MIXED_FP32_V  3   /* FP64 collocation and density contraction, so E_xc, N_e
                                 and the functional inputs are as in XC_FP64; Z and the
                                 V^j contraction in FP32 (FP32 MFMA, FP32 accumulate),

@@ -202,7 +202,8 @@ static int validate_inputs(const xc_molecule* mol, const xc_basis* basis,
 static int check_func_prec(int functional, int precision) {
     if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE)
         return fail(XC_ERR_UNSUPPORTED, "unknown functional");
-    if (precision != XC_FP64 && precision != XC_MIXED_FP32 && precision != XC_MIXED_FP32_V)
+    if (precision != XC_FP64 && precision != XC_MIXED_FP32 && precision != XC_MIXED_FP32_V &&
+        precision != XC_MIXED_BF16X3)
         return fail(XC_ERR_UNSUPPORTED, "precision not available");
     return XC_OK;
 }

@@ -292,7 +292,8 @@ int xc_engine_add_request(xc_engine* e, const xc_molecule* mol, const xc_basis* 
     if (!e || !req_id) return fail(XC_ERR_INVALID_ARG, "null engine or output");
     if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE)
         return fail(XC_ERR_UNSUPPORTED, "unknown functional");
-    if (precision != XC_FP64 && precision != XC_MIXED_FP32 && precision != XC_MIXED_FP32_V)
+    if (precision != XC_FP64 && precision != XC_MIXED_FP32 && precision != XC_MIXED_FP32_V &&
+        precision != XC_MIXED_BF16X3)
         return fail(XC_ERR_UNSUPPORTED, "precision not available");
     xc_device_opts o{e->stream, 0};
     xc_context* c = nullptr;

@@ -252,6 +252,70 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
     }
 }
 
+// Epilogue of the density contraction: the X tile (64 functions x 64
+// points, FP64) is in LDS. Each thread takes one point and 16 consecutive
+// functions (one row group per wave), re-evaluates phi (and grad phi) from
+// the shell data in FP64 and reduces phi*X (grad phi * X) into the per-row-
+// tile partials part[mt][q][point], q = rho, dx, dy, dz.
+template <bool GGA>
+__device__ inline void rho_epilogue(const WaveBatch& B, const ReqG& R, int m0, int n0, int mt,
+                                    double (*Xs)[kTile + 1], const int* fsh, const int* flmn,
+                                    char* scratch) {
+    const int tid = threadIdx.x;
+    const int c = tid & 63, g = tid >> 6;
+    const int col = n0 + c;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    if (col < B.ng) {
+        const double x = R.px[B.pt_off + col], y = R.py[B.pt_off + col],
+                     z = R.pz[B.pt_off + col];
+        int prev = -1;
+        double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
+        for (int rr = 0; rr < 16; ++rr) {
+            const int rl = g * 16 + rr;
+            if (m0 + rl >= B.nb) break;
+            // one row group per wave: the shell is wave-uniform
+            const int sidx = __builtin_amdgcn_readfirstlane(fsh[rl]);
+            if (sidx != prev) {
+                const ShellDev sh = load_shell(R.shells + sidx);
+                const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
+                shell_radial_wave(sh, R.palpha, R.pcoef, r2, rad, drad);
+                prev = sidx;
+            }
+            const int lmn = flmn[rl];
+            const double xv = Xs[rl][c];
+            if (GGA) {
+                double v, gx, gy, gz;
+                cart_eval(lmn & 15, (lmn >> 4) & 15, lmn >> 8, dx, dy, dz, rad, drad, v, gx,
+                          gy, gz);
+                q0 += v * xv;
+                q1 += gx * xv;
+                q2 += gy * xv;
+                q3 += gz * xv;
+            } else {
+                q0 += ipow3(dx, lmn & 15) * ipow3(dy, (lmn >> 4) & 15) *
+                      ipow3(dz, lmn >> 8) * rad * xv;
+            }
+        }
+    }
+    __syncthreads();
+    double* red = &Xs[0][0];
+    red[(g * 4 + 0) * kTile + c] = q0;
+    red[(g * 4 + 1) * kTile + c] = q1;
+    red[(g * 4 + 2) * kTile + c] = q2;
+    red[(g * 4 + 3) * kTile + c] = q3;
+    __syncthreads();
+    if (g == 0) {
+        double* part = (double*)(scratch + 8 * B.part_off);
+        constexpr int NQ = GGA ? 4 : 1;
+#pragma unroll
+        for (int qq = 0; qq < NQ; ++qq) {
+            const double v = red[(0 * 4 + qq) * kTile + c] + red[(1 * 4 + qq) * kTile + c] +
+                             red[(2 * 4 + qq) * kTile + c] + red[(3 * 4 + qq) * kTile + c];
+            part[(size_t)(mt * 4 + qq) * B.ngp + n0 + c] = v;
+        }
+    }
+}
+
 // ------------------------------------------------------- density (GEMM) ----
 // Tile of 64 functions x 64 points of X = P^j Phi^j; 4 waves, each a 32 x 32
 // block of 2 x 2 MFMA 16x16x4 tiles. A operand rows are gathered from the
@@ -429,58 +493,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
                     double(acc[mb][nb][r]);
     __syncthreads();
 
-    const int c = tid & 63, g = tid >> 6;
-    const int col = n0 + c;
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-    if (col < B.ng) {
-        const double x = R.px[B.pt_off + col], y = R.py[B.pt_off + col],
-                     z = R.pz[B.pt_off + col];
-        int prev = -1;
-        double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
-        for (int rr = 0; rr < 16; ++rr) {
-            const int rl = g * 16 + rr;
-            if (m0 + rl >= B.nb) break;
-            // one row group per wave: the shell is wave-uniform
-            const int sidx = __builtin_amdgcn_readfirstlane(fsh[rl]);
-            if (sidx != prev) {
-                const ShellDev sh = load_shell(R.shells + sidx);
-                const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
-                shell_radial_wave(sh, R.palpha, R.pcoef, r2, rad, drad);
-                prev = sidx;
-            }
-            const int lmn = flmn[rl];
-            const double xv = Xs[rl][c];
-            if (GGA) {
-                double v, gx, gy, gz;
-                cart_eval(lmn & 15, (lmn >> 4) & 15, lmn >> 8, dx, dy, dz, rad, drad, v, gx,
-                          gy, gz);
-                q0 += v * xv;
-                q1 += gx * xv;
-                q2 += gy * xv;
-                q3 += gz * xv;
-            } else {
-                q0 += ipow3(dx, lmn & 15) * ipow3(dy, (lmn >> 4) & 15) *
-                      ipow3(dz, lmn >> 8) * rad * xv;
-            }
-        }
-    }
-    __syncthreads();
-    double* red = &Xs[0][0];
-    red[(g * 4 + 0) * kTile + c] = q0;
-    red[(g * 4 + 1) * kTile + c] = q1;
-    red[(g * 4 + 2) * kTile + c] = q2;
-    red[(g * 4 + 3) * kTile + c] = q3;
-    __syncthreads();
-    if (g == 0) {
-        double* part = (double*)(scratch + 8 * B.part_off);
-        constexpr int NQ = GGA ? 4 : 1;
-#pragma unroll
-        for (int qq = 0; qq < NQ; ++qq) {
-            const double v = red[(0 * 4 + qq) * kTile + c] + red[(1 * 4 + qq) * kTile + c] +
-                             red[(2 * 4 + qq) * kTile + c] + red[(3 * 4 + qq) * kTile + c];
-            part[(size_t)(mt * 4 + qq) * B.ngp + n0 + c] = v;
-        }
-    }
+    rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, flmn, scratch);
 }
 
 // ------------------------------------------------- functional + Z matrix --
@@ -744,6 +757,343 @@ __global__ __launch_bounds__(256) void k_syr2k(
     }
 }
 
+// ----------------------------------------------- split-BF16 contractions --
+// Each operand x is split when it is stored to LDS into bf16 parts
+// hi = bf16(x) and lo = bf16(x - hi), and each product a b is formed as
+// hi hi + hi lo + lo hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
+// (the lo lo term and what lies below the two parts are dropped: about 16
+// significant bits per product). Operand lane l of the MFMA holds
+// A[l % 16][8 (l / 16) + t] and B[8 (l / 16) + t][l % 16], t = 0..7; the
+// accumulator layout is FP32's (row 4 (l / 16) + r). Tiles are 64 x 64 with
+// K steps of 32, stored k-contiguous with a row pitch of 40 bf16 so that the
+// 16-byte fragment reads of 16 lanes fall in distinct banks.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kKB = 32;        // K step of the split-BF16 kernels
+constexpr int kBP = kKB + 8;   // LDS row pitch in bf16
+
+__device__ inline void split_bf16(double x, __bf16& h, __bf16& l) {
+    h = (__bf16)(float)x;
+    l = (__bf16)(float)(x - (double)(float)h);
+}
+
+__device__ inline v4f mfma_bf16x3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                  const bf16x8& bl, v4f c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    return c;
+}
+
+// Density contraction X = P^j Phi^j in split BF16 (Phi stored in FP32), the
+// same tiles, gather and epilogue as k_gemm_rho.
+template <bool GGA>
+__global__ __launch_bounds__(256) void k_gemm_rho_bf16(
+    const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
+    const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
+    const int t = xcd_remap(blockIdx.x, ntiles);
+    const int2 tb = tmap[t];
+    const WaveBatch B = wb[tb.x];
+    const ReqG R = global_view(reqs[B.req]);
+    const gptr<const double> P = R.P;
+    const int nbf = R.nbf;
+    const int lt = tb.y;
+    const int ntn = B.ngp / kTile;
+    const int mt = lt / ntn, nt = lt - mt * ntn;
+    const int m0 = mt * kTile, n0 = nt * kTile;
+    const float* Phi = (const float*)(scratch + 8 * B.phi_off);
+    const gptr<const int> fl = R.func_list + B.func_off;
+
+    // four operand tiles (A, B) x (hi, lo), double-buffered; X in the epilogue
+    constexpr int kOpBytes = kTile * kBP * 2;
+    constexpr int kLds = 8 * kOpBytes;
+    static_assert(kLds >= kTile * (kTile + 1) * 8, "the X tile fits in the operand space");
+    __shared__ __attribute__((aligned(16))) char lds[kLds];
+    auto tile = [&](int which, int buf) {
+        return reinterpret_cast<__bf16 (*)[kBP]>(lds + (which * 2 + buf) * kOpBytes);
+    };
+    double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
+    __shared__ int frow[kTile], fsh[kTile], flmn[kTile];
+    __shared__ __attribute__((aligned(16))) int sfl[2][kKB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int nk = (B.nbp + kKB - 1) / kKB;
+    int fnext = -1;
+    auto fetch = [&](int ks) {
+        if (tid < kKB) {
+            const int k = ks * kKB + tid;
+            fnext = k < B.nb ? fl[k] : -1;
+        }
+    };
+    auto fput = [&](int slot) {
+        if (tid < kKB) sfl[slot][tid] = fnext;
+    };
+    fetch(0);
+    fput(0);
+    if (nk > 1) {
+        fetch(1);
+        fput(1);
+    }
+    if (tid < kTile) {
+        const int f = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
+        frow[tid] = f;
+        fsh[tid] = f >= 0 ? R.func_shell[f] : 0;
+        flmn[tid] = f >= 0 ? R.func_lmn[f] : 0;
+    }
+    __syncthreads();
+
+    // thread: row (function) or column (point) tid / 4, K offset 8 (tid % 4)
+    const int ar = tid >> 2, ak = (tid & 3) * 8;
+    const int fr = frow[ar];
+    const gptr<const double> Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
+    int fc[8];
+    double pv[8];
+    float bv[8];
+    auto fread = [&](int ks) {
+        const int4 u = *reinterpret_cast<const int4*>(&sfl[ks & 1][ak]);
+        const int4 v = *reinterpret_cast<const int4*>(&sfl[ks & 1][ak + 4]);
+        fc[0] = u.x; fc[1] = u.y; fc[2] = u.z; fc[3] = u.w;
+        fc[4] = v.x; fc[5] = v.y; fc[6] = v.z; fc[7] = v.w;
+    };
+    // loads go to valid (clamped) addresses; padding is zeroed at the store
+    auto gload = [&](int ks) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[q] = Prow[fc[q] >= 0 ? fc[q] : 0];
+        const int kb = ks * kKB + ak;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = kb + q;
+            bv[q] = Phi[(size_t)(k < B.nbp ? k : 0) * B.ngp + n0 + ar];
+        }
+    };
+    auto sstore = [&](int buf, int ks) {
+        bf16x8 h, l;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            __bf16 hq, lq;
+            split_bf16((fr >= 0 && fc[q] >= 0) ? pv[q] : 0.0, hq, lq);
+            h[q] = hq;
+            l[q] = lq;
+        }
+        *reinterpret_cast<bf16x8*>(&tile(0, buf)[ar][ak]) = h;
+        *reinterpret_cast<bf16x8*>(&tile(1, buf)[ar][ak]) = l;
+        const int kb = ks * kKB + ak;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            __bf16 hq, lq;
+            split_bf16(kb + q < B.nbp ? (double)bv[q] : 0.0, hq, lq);
+            h[q] = hq;
+            l[q] = lq;
+        }
+        *reinterpret_cast<bf16x8*>(&tile(2, buf)[ar][ak]) = h;
+        *reinterpret_cast<bf16x8*>(&tile(3, buf)[ar][ak]) = l;
+    };
+
+    v4f acc[2][2];
+    bool live[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+            live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + wn * 32 + nb * 16 < B.ng);
+        }
+
+    fread(0);
+    gload(0);
+    sstore(0, 0);
+    if (nk > 2) fetch(2);
+    __syncthreads();
+    const int fk = 8 * (lane >> 4);
+    for (int ks = 0; ks < nk; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < nk) {
+            fread(ks + 1);
+            gload(ks + 1);
+        }
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int r = wm * 32 + mb * 16 + (lane & 15);
+            ah[mb] = *reinterpret_cast<const bf16x8*>(&tile(0, cur)[r][fk]);
+            al[mb] = *reinterpret_cast<const bf16x8*>(&tile(1, cur)[r][fk]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int cc = wn * 32 + nb * 16 + (lane & 15);
+            bh[nb] = *reinterpret_cast<const bf16x8*>(&tile(2, cur)[cc][fk]);
+            bl[nb] = *reinterpret_cast<const bf16x8*>(&tile(3, cur)[cc][fk]);
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+                if (live[mb][nb])
+                    acc[mb][nb] = mfma_bf16x3(ah[mb], al[mb], bh[nb], bl[nb], acc[mb][nb]);
+        if (ks + 1 < nk) sstore(cur ^ 1, ks + 1);
+        if (ks + 2 < nk) {
+            fput(ks & 1);
+            if (ks + 3 < nk) fetch(ks + 3);
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Xs[wm * 32 + mb * 16 + 4 * (lane >> 4) + r][wn * 32 + nb * 16 + (lane & 15)] =
+                    double(acc[mb][nb][r]);
+    __syncthreads();
+    rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, flmn, scratch);
+}
+
+// Potential contraction V^j = Z Phi^T + Phi Z^T in split BF16 (Phi and Z
+// stored in FP32), lower-triangle tiles as in k_syr2k, one LDS buffer with
+// the next step's loads in registers.
+__global__ __launch_bounds__(256) void k_syr2k_bf16(
+    const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
+    const ReqDev* __restrict__ reqs, const char* __restrict__ scratch) {
+    const int t = xcd_remap(blockIdx.x, ntiles);
+    const int2 tb = tmap[t];
+    const WaveBatch B = wb[tb.x];
+    const ReqG R = global_view(reqs[B.req]);
+    const gptr<const int> func_list = R.func_list;
+    const gptr<double> V = R.V;
+    const int nbf = R.nbf;
+    const int lt = tb.y;
+    int I = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= lt) ++I;
+    while (I * (I + 1) / 2 > lt) --I;
+    const int J = lt - I * (I + 1) / 2;
+    const size_t slab = (size_t)B.nbp * B.ngp;
+    const float* Phi = (const float*)(scratch + 8 * B.phi_off);
+    const float* Zm = (const float*)(scratch + 8 * (B.phi_off + (long long)slab));
+    const gptr<const int> fl = func_list + B.func_off;
+
+    // ZI, PI, PJ, ZJ, each (hi, lo): one buffer
+    constexpr int kOpBytes = kTile * kBP * 2;
+    __shared__ __attribute__((aligned(16))) char lds[8 * kOpBytes];
+    auto tile = [&](int which) {
+        return reinterpret_cast<__bf16 (*)[kBP]>(lds + which * kOpBytes);
+    };
+    __shared__ int sfI[kTile], sfJ[kTile];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < kTile) {
+        const int r = I * kTile + tid;
+        sfI[tid] = r < B.nb ? fl[r] : -1;
+    } else if (tid < 2 * kTile) {
+        const int r = J * kTile + tid - kTile;
+        sfJ[tid - kTile] = r < B.nb ? fl[r] : -1;
+    }
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    const int rI = I * kTile + lr, rJ = J * kTile + lr;
+    const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
+    const float* src[4] = {Zm + (size_t)(vI ? rI : 0) * B.ngp, Phi + (size_t)(vI ? rI : 0) * B.ngp,
+                           Phi + (size_t)(vJ ? rJ : 0) * B.ngp, Zm + (size_t)(vJ ? rJ : 0) * B.ngp};
+    const bool valid[4] = {vI, vI, vJ, vJ};
+    float4 g[4][2];
+    auto gload = [&](int ks) {
+        const int k0 = ks * kKB + lk;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            g[a][0] = *reinterpret_cast<const float4*>(src[a] + k0);
+            g[a][1] = *reinterpret_cast<const float4*>(src[a] + k0 + 4);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const float x[8] = {g[a][0].x, g[a][0].y, g[a][0].z, g[a][0].w,
+                                g[a][1].x, g[a][1].y, g[a][1].z, g[a][1].w};
+            bf16x8 h, l;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                __bf16 hq, lq;
+                split_bf16(valid[a] ? (double)x[q] : 0.0, hq, lq);
+                h[q] = hq;
+                l[q] = lq;
+            }
+            *reinterpret_cast<bf16x8*>(&tile(2 * a)[lr][lk]) = h;
+            *reinterpret_cast<bf16x8*>(&tile(2 * a + 1)[lr][lk]) = l;
+        }
+    };
+
+    v4f acc[2][2];
+    bool live[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+            const int r0 = I * kTile + wm * 32 + mb * 16;
+            const int c0 = J * kTile + wn * 32 + nb * 16;
+            live[mb][nb] = (r0 < B.nb) && (c0 < B.nb) && (c0 <= r0 + 15);
+        }
+    // the points beyond n_g are zero padding, and n_gp is a multiple of 64:
+    // K steps of 32 up to n_g stay inside the slab rows
+    const int nk = (B.ng + kKB - 1) / kKB;
+    gload(0);
+    sstore();
+    __syncthreads();
+    const int fk = 8 * (lane >> 4);
+    for (int ks = 0; ks < nk; ++ks) {
+        if (ks + 1 < nk) gload(ks + 1);
+        bf16x8 zih[2], zil[2], pih[2], pil[2], pjh[2], pjl[2], zjh[2], zjl[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int r = wm * 32 + mb * 16 + (lane & 15);
+            zih[mb] = *reinterpret_cast<const bf16x8*>(&tile(0)[r][fk]);
+            zil[mb] = *reinterpret_cast<const bf16x8*>(&tile(1)[r][fk]);
+            pih[mb] = *reinterpret_cast<const bf16x8*>(&tile(2)[r][fk]);
+            pil[mb] = *reinterpret_cast<const bf16x8*>(&tile(3)[r][fk]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int r = wn * 32 + nb * 16 + (lane & 15);
+            pjh[nb] = *reinterpret_cast<const bf16x8*>(&tile(4)[r][fk]);
+            pjl[nb] = *reinterpret_cast<const bf16x8*>(&tile(5)[r][fk]);
+            zjh[nb] = *reinterpret_cast<const bf16x8*>(&tile(6)[r][fk]);
+            zjl[nb] = *reinterpret_cast<const bf16x8*>(&tile(7)[r][fk]);
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                if (!live[mb][nb]) continue;
+                acc[mb][nb] = mfma_bf16x3(zih[mb], zil[mb], pjh[nb], pjl[nb], acc[mb][nb]);
+                acc[mb][nb] = mfma_bf16x3(pih[mb], pil[mb], zjh[nb], zjl[nb], acc[mb][nb]);
+            }
+        __syncthreads();
+        if (ks + 1 < nk) {
+            sstore();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int tr = wm * 32 + mb * 16 + 4 * (lane >> 4) + r;
+            const int row = I * kTile + tr;
+            if (row >= B.nb) continue;
+            const gptr<double> vrow = V + (size_t)sfI[tr] * nbf;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int tc = wn * 32 + nb * 16 + (lane & 15);
+                const int col = J * kTile + tc;
+                if (col < B.nb && col <= row)
+                    __hip_atomic_fetch_add(vrow + sfJ[tc], double(acc[mb][nb][r]),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- misc ----
 // Tile -> (batch, tile within the batch) for one launch over nwb batches whose
 // tile counts have the exclusive prefix `prefix`: one thread per batch.
@@ -837,6 +1187,42 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
     return XC_OK;
 }
 
+// Split-BF16 mode: Phi and Z stored in FP32, both contractions split BF16.
+template <bool GGA>
+static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
+                            const int* gpre, const int* spre, int count, int gemm_tiles,
+                            int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap) {
+    {
+        PhaseScope ps(timer, s, XC_PHASE_COLLOC);
+        hipLaunchKernelGGL((k_colloc<float>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        XC_HIP(hipGetLastError());
+    }
+    if (gemm_tiles > 0) {
+        PhaseScope ps(timer, s, XC_PHASE_DENSITY);
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, gpre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_gemm_rho_bf16<GGA>), dim3(gemm_tiles), dim3(256), 0, s, b,
+                           (const int2*)tmap, gemm_tiles, reqs, scr);
+        XC_HIP(hipGetLastError());
+    }
+    {
+        PhaseScope ps(timer, s, XC_PHASE_FUNCTIONAL);
+        hipLaunchKernelGGL((k_func_z<GGA, float>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        XC_HIP(hipGetLastError());
+    }
+    if (syr_tiles > 0) {
+        PhaseScope ps(timer, s, XC_PHASE_POTENTIAL);
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, spre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_syr2k_bf16, dim3(syr_tiles), dim3(256), 0, s, b,
+                           (const int2*)tmap, syr_tiles, reqs, (const char*)scr);
+        XC_HIP(hipGetLastError());
+    }
+    return XC_OK;
+}
+
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre, int count,
                 int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch,
@@ -849,6 +1235,11 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                    : launch_wave_t<false, float, float>(timer, s, d_wb, d_gpre, d_spre,
                                                         count, gemm_tiles, syr_tiles, d_reqs,
                                                         scratch, d_tmap);
+    if (precision == XC_MIXED_BF16X3)
+        return gga ? launch_wave_bf16<true>(timer, s, d_wb, d_gpre, d_spre, count, gemm_tiles,
+                                            syr_tiles, d_reqs, scratch, d_tmap)
+                   : launch_wave_bf16<false>(timer, s, d_wb, d_gpre, d_spre, count,
+                                             gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap);
     if (precision == XC_MIXED_FP32_V)
         return gga ? launch_wave_t<true, double, float>(timer, s, d_wb, d_gpre, d_spre, count,
                                                         gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap)

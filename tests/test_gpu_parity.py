@@ -237,6 +237,22 @@ def test_mixed_fp32_error_vs_oracle(functional):
 
 
 @pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_mixed_bf16x3_error_vs_oracle(functional):
+    """Split-BF16 contractions (about 16 significant bits per product, FP32
+    accumulation), FP64 functional and sums: errors against the FP64 oracle
+    are reported and bounded."""
+    w = cfg_water()
+    say(f"case water {functional} bf16x3")
+    from gpu_util import gpu_integrate_prec
+    E, N, V, st = gpu_integrate_prec(w, functional, "bf16x3")
+    Eo, No, Vo = oracle_integrate(w, functional)
+    say(f"  bf16x3: dE {E - Eo:.3e} dN {N - No:.3e} max dV {np.abs(V - Vo).max():.3e}")
+    assert abs(E - Eo) <= 1e-3 and abs(N - No) <= 1e-3
+    assert np.abs(V - Vo).max() <= 1e-2
+    assert np.array_equal(V, V.T)
+
+
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
 def test_mixed_fp32_potential_error_vs_oracle(functional):
     """FP64 collocation and density contraction, FP32 Z and potential
     contraction: E_xc and N_e equal the FP64 path's bit for bit (and so meet

@@ -615,14 +615,17 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const T* Zm = (const T*)(scratch + 8 * (B.phi_off + (long long)slab));
     const gptr<const int> fl = func_list + B.func_off;
 
-    // K steps of 8 keep the four double-buffered operand tiles at 37 KB of
-    // LDS, so four workgroups fit on a CU.
+    // K steps of 8. FP64: one LDS buffer (the next step's operands wait in
+    // registers), 19 KB, so the register count (five workgroups per CU) sets
+    // the occupancy, not LDS (four with two buffers: measured slower). FP32
+    // arithmetic: two buffers (measured faster there).
     constexpr int KS = 8;
     // row pitch: 9 doubles, or 12 floats (the 4-byte operand reads of a wave
     // then fall in distinct banks)
     constexpr int KP = sizeof(T) == 8 ? KS + 1 : KS + 4;
-    __shared__ T sZI[2][kTile][KP], sPI[2][kTile][KP];
-    __shared__ T sPJ[2][kTile][KP], sZJ[2][kTile][KP];
+    constexpr int NBUF = sizeof(T) == 8 ? 1 : 2;
+    __shared__ T sZI[NBUF][kTile][KP], sPI[NBUF][kTile][KP];
+    __shared__ T sPJ[NBUF][kTile][KP], sZJ[NBUF][kTile][KP];
     // global function indices of the tile's rows and columns (-1: padding)
     __shared__ int sfI[kTile], sfJ[kTile];
 
@@ -707,7 +710,7 @@ __global__ __launch_bounds__(256) void k_syr2k(
     sstore(0);
     __syncthreads();
     for (int ks = 0; ks < nk; ++ks) {
-        const int cur = ks & 1;
+        const int cur = NBUF == 1 ? 0 : (ks & 1);
         if (ks + 1 < nk) gload(ks + 1);
 #pragma unroll
         for (int kk = 0; kk < KS / 4; ++kk) {
@@ -734,8 +737,16 @@ __global__ __launch_bounds__(256) void k_syr2k(
                     acc[mb][nb] = M::mma(ap[mb], bz[nb], acc[mb][nb]);
                 }
         }
-        if (ks + 1 < nk) sstore(cur ^ 1);
-        __syncthreads();
+        if constexpr (NBUF == 1) {
+            __syncthreads();
+            if (ks + 1 < nk) {
+                sstore(0);
+                __syncthreads();
+            }
+        } else {
+            if (ks + 1 < nk) sstore(cur ^ 1);
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {

@@ -59,17 +59,6 @@ __device__ inline int xcd_remap(int bid, int nblk) {
                        : rem * (base + 1) + (xcd - rem) * base + idx;
 }
 
-// Largest b in [0, n) with prefix[b] <= t (prefix ascending, prefix[0] = 0).
-__device__ inline int find_segment(const int* prefix, int n, int t) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Pointers that kernels read out of device-side descriptors are generic to
 // the compiler, so their loads and atomics become flat instructions. Flat
 // operations also count against the LDS wait counter: a wait for LDS data

@@ -406,16 +406,26 @@ __global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const in
             }
         }
         wave_argmin(dmin, bmin);
-        // P_C = prod_{B != C} s(mu_CB), spread over the lanes
+        // P_C = prod_{B != C} s(mu_CB), spread over the lanes. If any
+        // mu_CB >= a the product is exactly zero: a wave vote skips the
+        // polynomials and the reduction (about half the candidates).
         auto cell = [&](int C) {
             const double dC = sqrt(dist2_to(sat[C], px, py, pz));
             const double* ir = invR + (size_t)C * natoms;
-            double p = 1.0;
+            double mu[NPER];
+            bool zero = false;
 #pragma unroll
             for (int j = 0; j < NPER; ++j) {
                 const int B = lane + 64 * j;
-                if (B < natoms && B != C) p *= ssf_s_inv((dC - d[j]) * ir[B], a, inv_a);
+                const bool use = B < natoms && B != C;
+                // s(-a) = 1 exactly stands in for the absent factors
+                mu[j] = use ? (dC - d[j]) * ir[use ? B : 0] : -a;
+                zero = zero || mu[j] >= a;
             }
+            if (__any(zero)) return 0.0;
+            double p = 1.0;
+#pragma unroll
+            for (int j = 0; j < NPER; ++j) p *= ssf_s_inv(mu[j], a, inv_a);
             return wave_product(p);
         };
         const double PA = cell(pA);

@@ -76,34 +76,47 @@ def make_workload(name):
 
 
 def cpu_baseline(w, functional, stride):
-    """The oracle, as it is, on a strided sample of parent atom 0's grid."""
+    """The oracle, as it is, on a strided sample of parent atom 0's grid, with
+    the BLAS threads it gets by default (all cores), and once more with one
+    thread on a sample 8 times sparser."""
     import oracle
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
     mask = np.zeros(w.natoms, bool)
     mask[0] = True
-    sl = slice(0, None, stride)
     n_atom = w.n_rad * w.n_ang
-    n_sample = len(range(*sl.indices(n_atom)))
-    t0 = time.perf_counter()
-    oracle.integrate(w.coords, w.mk_alpha, w.basis, w.P, functional, w.n_rad, w.ang,
-                     atom_mask=mask, point_slice=sl,
-                     progress=lambda s, d, t: log(f"  oracle {s} {d}/{t}"))
-    dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "grid points/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{n_sample} points (every {stride}th point of parent atom 0's "
-                      f"{n_atom}-point grid) of the same workload, SSF over all "
-                      f"{w.natoms} atoms, {w.nbf} functions, {functional}; "
-                      f"{dt:.1f} s"}
+
+    def run(st):
+        sl = slice(0, None, st)
+        n = len(range(*sl.indices(n_atom)))
+        t0 = time.perf_counter()
+        oracle.integrate(w.coords, w.mk_alpha, w.basis, w.P, functional, w.n_rad, w.ang,
+                         atom_mask=mask, point_slice=sl,
+                         progress=lambda s, d, t: log(f"  oracle {s} {d}/{t}"))
+        return n, time.perf_counter() - t0
+
+    n_sample, dt = run(stride)
+    out = {"value": n_sample / dt, "unit": "grid points/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"{n_sample} points (every {stride}th point of parent atom 0's "
+                     f"{n_atom}-point grid) of the same workload, SSF over all "
+                     f"{w.natoms} atoms, {w.nbf} functions, {functional}; "
+                     f"{dt:.1f} s"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, dt1 = run(8 * stride)
+        out["value_1_thread"] = n1 / dt1
+        out["sample_1_thread"] = f"{n1} points (every {8 * stride}th), {dt1:.1f} s"
+    return out
 
 
-def serving_run(n_req, warm_pts_per_s, seed=5, log_every=0):
+def serving_run(n_req, warm_pts_per_s, seed=5, load=0.7):
     """The serving stream: n_req requests (1-100 waters, LDA/PBE, 6-12 SCF
-    iterations, 75 x 302 grid) with Poisson arrivals at 0.7 x the rate the
+    iterations, 75 x 302 grid) with Poisson arrivals at `load` x the rate the
     warm FP64 throughput could sustain; densities made on the device."""
     import torch
     from paper_2007_03143_amd.serving import ServeRequest, DeviceDensities, serve
@@ -112,7 +125,7 @@ def serving_run(n_req, warm_pts_per_s, seed=5, log_every=0):
     import oracle
     stream = serving_stream(n_req, seed=seed)
     mean_pts = np.mean([w.n_points_nominal * n for w, n, _ in stream])
-    lam = 0.7 * warm_pts_per_s / mean_pts
+    lam = load * warm_pts_per_s / mean_pts
     rng = np.random.default_rng([seed, 99])
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
     arrivals -= arrivals[0]
@@ -137,7 +150,7 @@ def serving_run(n_req, warm_pts_per_s, seed=5, log_every=0):
         E, N, V = r.results[0]
         checks.append({"request": i, "name": r.name, "dE_xc": E - Eo, "dN_e": N - No,
                        "max_dV": float(np.abs(V - Vo).max())})
-    summary.update({"requests": n_req, "arrival_rate_per_s": lam,
+    summary.update({"requests": n_req, "load": load, "arrival_rate_per_s": lam,
                     "mean_points_per_request": mean_pts, "oracle_checks": checks,
                     "grid": "75x302", "wave_bytes": 2 << 30})
     return summary
@@ -156,6 +169,9 @@ def main():
     ap.add_argument("--mixed", default="fp32,fp32v,bf16x3")
     ap.add_argument("--serving", type=int, default=40,
                     help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serving-loads", default="0.7",
+                    help="arrival rates as fractions of the closed-loop rate; the first "
+                         "is reported as 'serving', all of them in 'serving_sweep'")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 3 times (a plain "
                          "copy kernel of known size for scaling HBM byte counters)")
@@ -304,10 +320,20 @@ def main():
     del P
     torch.cuda.empty_cache()
     if args.serving > 0:
-        log(f"serving stream of {args.serving} requests")
-        out["serving"] = serving_run(args.serving, n_nom / (ms_warm * 1e-3))
-        log(f"serving: p50 {out['serving']['latency_p50_ms']:.1f} ms "
-            f"p99 {out['serving']['latency_p99_ms']:.1f} ms")
+        loads = [float(x) for x in args.serving_loads.split(",")]
+        sweep = []
+        for ld in loads:
+            log(f"serving stream of {args.serving} requests at {ld} x the closed-loop rate")
+            res = serving_run(args.serving, n_nom / (ms_warm * 1e-3), load=ld)
+            log(f"serving: p50 {res['latency_p50_ms']:.1f} ms p99 {res['latency_p99_ms']:.1f} ms")
+            sweep.append(res)
+        out["serving"] = sweep[0]
+        if len(sweep) > 1:
+            out["serving_sweep"] = [
+                {k: r[k] for k in ("load", "arrival_rate_per_s", "points_per_s",
+                                   "latency_p50_ms", "latency_p99_ms",
+                                   "request_latency_p50_s", "request_latency_p99_s",
+                                   "wall_s", "integrations")} for r in sweep]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(w, functional, args.cpu_stride)

@@ -114,10 +114,11 @@ def cpu_baseline(w, functional, stride):
     return out
 
 
-def serving_run(n_req, warm_pts_per_s, seed=5, load=0.7):
+def serving_run(n_req, seed=5, load=0.7, saturation=None):
     """The serving stream: n_req requests (1-100 waters, LDA/PBE, 6-12 SCF
-    iterations, 75 x 302 grid) with Poisson arrivals at `load` x the rate the
-    warm FP64 throughput could sustain; densities made on the device."""
+    iterations, 75 x 302 grid), densities made on the device. Arrivals are
+    Poisson at `load` x the stream's closed-loop saturation rate, which is
+    measured first (all requests submitted at once) unless given."""
     import torch
     from paper_2007_03143_amd.serving import ServeRequest, DeviceDensities, serve
     from workloads import grid_spec_dict
@@ -125,16 +126,22 @@ def serving_run(n_req, warm_pts_per_s, seed=5, load=0.7):
     import oracle
     stream = serving_stream(n_req, seed=seed)
     mean_pts = np.mean([w.n_points_nominal * n for w, n, _ in stream])
-    lam = load * warm_pts_per_s / mean_pts
+
+    def requests(arrivals):
+        return [ServeRequest(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w), w.functional,
+                             DeviceDensities(w.nbf, w.n_occ, n_iter, dseed), arrival=float(t),
+                             name=w.name, n_points_nominal=w.n_points_nominal)
+                for (w, n_iter, dseed), t in zip(stream, arrivals)]
+
+    if saturation is None:
+        closed = serve(requests(np.zeros(n_req)), wave_bytes=2 << 30)
+        saturation = closed["points_per_s"]
+        log(f"serving: closed-loop {saturation / 1e6:.1f} Mpts/s")
+    lam = load * saturation / mean_pts
     rng = np.random.default_rng([seed, 99])
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
     arrivals -= arrivals[0]
-    reqs = []
-    for (w, n_iter, dseed), t in zip(stream, arrivals):
-        reqs.append(ServeRequest(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w),
-                                 w.functional, DeviceDensities(w.nbf, w.n_occ, n_iter, dseed),
-                                 arrival=float(t), name=w.name,
-                                 n_points_nominal=w.n_points_nominal))
+    reqs = requests(arrivals)
     small = [i for i, (w, _, _) in enumerate(stream) if w.natoms <= 12]
     n_check = max(1, int(round(0.05 * n_req)))
     check = sorted(rng.choice(small, size=min(n_check, len(small)), replace=False).tolist()) \
@@ -151,6 +158,7 @@ def serving_run(n_req, warm_pts_per_s, seed=5, load=0.7):
         checks.append({"request": i, "name": r.name, "dE_xc": E - Eo, "dN_e": N - No,
                        "max_dV": float(np.abs(V - Vo).max())})
     summary.update({"requests": n_req, "load": load, "arrival_rate_per_s": lam,
+                    "saturation_points_per_s": saturation,
                     "mean_points_per_request": mean_pts, "oracle_checks": checks,
                     "grid": "75x302", "wave_bytes": 2 << 30})
     return summary
@@ -322,15 +330,18 @@ def main():
     if args.serving > 0:
         loads = [float(x) for x in args.serving_loads.split(",")]
         sweep = []
+        sat = None
         for ld in loads:
             log(f"serving stream of {args.serving} requests at {ld} x the closed-loop rate")
-            res = serving_run(args.serving, n_nom / (ms_warm * 1e-3), load=ld)
+            res = serving_run(args.serving, load=ld, saturation=sat)
+            sat = res["saturation_points_per_s"]
             log(f"serving: p50 {res['latency_p50_ms']:.1f} ms p99 {res['latency_p99_ms']:.1f} ms")
             sweep.append(res)
         out["serving"] = sweep[0]
         if len(sweep) > 1:
             out["serving_sweep"] = [
-                {k: r[k] for k in ("load", "arrival_rate_per_s", "points_per_s",
+                {k: r[k] for k in ("load", "arrival_rate_per_s", "saturation_points_per_s",
+                                   "points_per_s",
                                    "latency_p50_ms", "latency_p99_ms",
                                    "request_latency_p50_s", "request_latency_p99_s",
                                    "wall_s", "integrations")} for r in sweep]

@@ -354,14 +354,14 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     T (*Bs)[16][kTile + 1] = reinterpret_cast<T (*)[16][kTile + 1]>(lds + kABytes);
     double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
     __shared__ int frow[kTile], fsh[kTile], flmn[kTile];
-    // function indices (columns of P) of two consecutive K steps
-    __shared__ __attribute__((aligned(16))) int sfl[2][16];
+    // function indices (columns of P) of four consecutive K steps
+    __shared__ __attribute__((aligned(16))) int sfl[4][16];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int nk = B.nbp / 16;
     // The 16 column indices of a K step are loaded once, by threads 0-15,
-    // two steps ahead, and passed on through LDS.
+    // and passed on through a ring of four LDS slots (slot = step mod 4).
     int fnext = -1;
     auto fetch = [&](int ks) {
         if (tid < 16) {
@@ -369,14 +369,12 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
             fnext = k < B.nb ? fl[k] : -1;
         }
     };
-    auto fput = [&](int slot) {
-        if (tid < 16) sfl[slot][tid] = fnext;
+    auto fput = [&](int ks) {
+        if (tid < 16) sfl[ks & 3][tid] = fnext;
     };
-    fetch(0);
-    fput(0);
-    if (nk > 1) {
-        fetch(1);
-        fput(1);
+    for (int s0 = 0; s0 < 3 && s0 < nk; ++s0) {
+        fetch(s0);
+        fput(s0);
     }
     if (tid < kTile) {
         const int f = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
@@ -391,43 +389,47 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int fr = frow[ar];
     const gptr<const double> Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
 
-    // The P^j columns of a K step are gathered through the function list.
-    T ra[4], rb[4];
-    int fc[4];
-    auto fread = [&](int ks) {
-        const int4 v = *reinterpret_cast<const int4*>(&sfl[ks & 1][ac]);
-        fc[0] = v.x;
-        fc[1] = v.y;
-        fc[2] = v.z;
-        fc[3] = v.w;
+    // Two register sets: the operands of step ks + 2 are loaded while step
+    // ks is computed and those of step ks + 1 wait in the other set. The P^j
+    // columns of a step are gathered through the function list. FP32: the P
+    // values stay FP64 until the LDS store, where they are rounded and the
+    // padding is selected away, all loads going to valid (clamped) addresses.
+    struct Regs {
+        T ra[4], rb[4];
+        double pv[4];
+        int fc[4];
     };
-    // FP32: the P values stay FP64 in registers until the LDS store, where
-    // they are rounded and the padding is selected away; all four loads go
-    // to valid (clamped) addresses. (A conversion right after each load, in
-    // a branch around it, made every load wait for the one before.)
-    double pv[4];
-    auto gload = [&](int ks) {
+    Regs RA, RB;
+    auto fread = [&](Regs& r, int ks) {
+        const int4 v = *reinterpret_cast<const int4*>(&sfl[ks & 3][ac]);
+        r.fc[0] = v.x;
+        r.fc[1] = v.y;
+        r.fc[2] = v.z;
+        r.fc[3] = v.w;
+    };
+    auto gload = [&](Regs& r, int ks) {
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pv[q] = Prow[fc[q] >= 0 ? fc[q] : 0];
+            for (int q = 0; q < 4; ++q) r.pv[q] = Prow[r.fc[q] >= 0 ? r.fc[q] : 0];
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                ra[q] = (fr >= 0 && fc[q] >= 0) ? T(Prow[fc[q]]) : T(0);
+                r.ra[q] = (fr >= 0 && r.fc[q] >= 0) ? T(Prow[r.fc[q]]) : T(0);
         }
         const T* src = Phi + (size_t)(ks * 16 + br) * B.ngp + n0 + bc;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rb[q] = src[q];
+        for (int q = 0; q < 4; ++q) r.rb[q] = src[q];
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](Regs& r, int buf) {
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) ra[q] = (fr >= 0 && fc[q] >= 0) ? T(pv[q]) : T(0);
+            for (int q = 0; q < 4; ++q)
+                r.ra[q] = (fr >= 0 && r.fc[q] >= 0) ? T(r.pv[q]) : T(0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            As[buf][ar][ac + q] = ra[q];
-            Bs[buf][br][bc + q] = rb[q];
+            As[buf][ar][ac + q] = r.ra[q];
+            Bs[buf][br][bc + q] = r.rb[q];
         }
     };
 
@@ -446,16 +448,23 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         for (int nb = 0; nb < 2; ++nb)
             live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + wn * 32 + nb * 16 < B.ng);
 
-    fread(0);
-    gload(0);
-    sstore(0);
-    if (nk > 2) fetch(2);
+    fread(RA, 0);
+    gload(RA, 0);
+    sstore(RA, 0);
+    if (nk > 1) {
+        fread(RB, 1);
+        gload(RB, 1);
+    }
+    if (nk > 3) fetch(3);
     __syncthreads();
-    for (int ks = 0; ks < nk; ++ks) {
+    // step ks: load step ks + 2 into rl, compute from LDS buffer ks & 1,
+    // store step ks + 1 from rs into the other buffer; then refill the ring
+    // slot of step ks + 3 (last read three steps ago) and fetch step ks + 4
+    auto step = [&](int ks, Regs& rl, Regs& rs) {
         const int cur = ks & 1;
-        if (ks + 1 < nk) {
-            fread(ks + 1);
-            gload(ks + 1);
+        if (ks + 2 < nk) {
+            fread(rl, ks + 2);
+            gload(rl, ks + 2);
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -472,14 +481,16 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
                 for (int nb = 0; nb < 2; ++nb)
                     if (live[mb][nb]) acc[mb][nb] = M::mma(a[mb], b[nb], acc[mb][nb]);
         }
-        if (ks + 1 < nk) sstore(cur ^ 1);
-        // slot ks & 1 was last read in the previous step: refill it with the
-        // indices of step ks + 2, then start the load for step ks + 3
-        if (ks + 2 < nk) {
-            fput(ks & 1);
-            if (ks + 3 < nk) fetch(ks + 3);
+        if (ks + 1 < nk) sstore(rs, cur ^ 1);
+        if (ks + 3 < nk) {
+            fput(ks + 3);
+            if (ks + 4 < nk) fetch(ks + 4);
         }
         __syncthreads();
+    };
+    for (int ks = 0; ks < nk; ks += 2) {
+        step(ks, RA, RB);
+        if (ks + 1 < nk) step(ks + 1, RB, RA);
     }
 
     // spill X (the loop ended on a barrier, so the operand tiles are free)

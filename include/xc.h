@@ -55,9 +55,10 @@ extern "C" {
 
 /* arithmetic of the collocation and the two batched contractions */
 #define XC_FP64          0   /* everything FP64 */
-#define XC_MIXED_FP32    1   /* FP32 collocation and contractions (FP32 MFMA, FP32
-                                accumulate); FP64 functional, Z formation, E_xc/N_e
-                                sums and V accumulation */
+#define XC_MIXED_FP32    1   /* Phi and Z formed in FP64 and stored in FP32; both
+                                contractions on FP32 MFMA with FP32 accumulation;
+                                FP64 functional, Z formation, E_xc/N_e sums and V
+                                accumulation */
 #define XC_MIXED_BF16X3  2   /* Phi and Z stored in FP32; both contractions in split
                                 BF16 (x = hi + lo, products hi hi + hi lo + lo hi on
                                 BF16 MFMA, FP32 accumulate); FP64 functional, Z
@@ -130,9 +131,9 @@ typedef struct xc_grid_spec {
  *  stream      hipStream_t every launch and copy of the context is ordered
  *              on (NULL: the null stream). The library never changes stream
  *              priorities.
- *  wave_bytes  budget of device scratch for one wave of batches (the paper's
- *              "saturate device memory" subsets, Alg. 2); 0 picks a default
- *              from the free device memory.
+ *  wave_bytes  budget of device scratch for one wave of batches (the
+ *              subsets of batches that fill the device memory, Alg. 2); 0:
+ *              min(half the free device memory, 48 GiB).
  */
 typedef struct xc_device_opts {
     void* stream;
@@ -169,7 +170,7 @@ typedef struct xc_stats {
 #define XC_PHASE_COMPACT    2   /* removal of zero-weight points */
 #define XC_PHASE_BATCH      3   /* cuboid batching */
 #define XC_PHASE_SCREEN     4   /* shell screening (Alg. 1) */
-#define XC_PHASE_COLLOC     5   /* collocation Phi, grad Phi */
+#define XC_PHASE_COLLOC     5   /* collocation Phi (grad Phi is re-evaluated where used) */
 #define XC_PHASE_DENSITY    6   /* X = P Phi on MFMA with rho, grad rho epilogue */
 #define XC_PHASE_FUNCTIONAL 7   /* functional, E_xc/N_e partials, Z */
 #define XC_PHASE_POTENTIAL  8   /* V = Z Phi^T + Phi Z^T on MFMA with scatter-add */

@@ -207,7 +207,7 @@ def test_cluster_sampled_atoms_parity(atom):
 
 def test_chain600_sampled_atoms_parity():
     """The 600-atom polypeptide-like chain (6280 functions with the diffuse
-    shell): more atoms than the SSF kernel stages in LDS and a large P. The
+    shell): ten atoms per lane in the partition kernel and a large P. The
     radial x angular grid is reduced (30 x 50) so that the oracle's all-pairs
     partition over the two sampled parent atoms (a C and an H) stays short;
     the GPU still builds, partitions and batches every atom's grid."""

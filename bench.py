@@ -10,7 +10,9 @@ weights, removal of zero-weight points, batching, shell screening, wave
 plan, collocation, X = P Phi with rho/grad rho, functional, Z, and
 V = Z Phi^T + Phi Z^T with scatter-add, mirror and the E_xc/N_e sums.
 value = nominal grid points / step time. The same line reports the warm
-(grid reused, Sec. 2.3.1) rate, the roofline of the dominant kernel from
+(grid reused, Sec. 2.3.1) rate, with and without Phi kept between
+integrations, the point-weighted histogram of the screened function counts
+n_b, the mixed-precision runs, the roofline of the dominant kernel from
 HIP-event timing inside the timed region, and the CPU oracle timed on a
 bounded sample of the same workload.
 
@@ -40,6 +42,20 @@ def source_sha256(rel):
     import hashlib
     with open(os.path.join(HERE, rel), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
+
+
+def nb_histogram(ctx, w, width=128):
+    """Share of the kept points in batches whose screened function count
+    n_b falls in [k * width, (k + 1) * width)."""
+    pp, _, sp, sh = ctx.export_batches()
+    nf = w.basis.shell_nfunc[sh]
+    csum = np.concatenate(([0], np.cumsum(nf)))
+    nb = csum[sp[1:]] - csum[sp[:-1]]
+    ng = np.diff(pp)
+    h = np.bincount(nb // width, weights=ng)
+    tot = max(float(ng.sum()), 1.0)
+    return {f"{k * width}-{(k + 1) * width - 1}": round(float(v) / tot, 4)
+            for k, v in enumerate(h) if v > 0}
 
 
 def profiled_traffic(kernel, workload, sha):
@@ -248,6 +264,29 @@ def main():
     V = ctx.V.cpu().numpy()
     log(f"warm {ms_warm:.1f} ms/step; E_xc {EN[0]!r} N_e {EN[1]!r}")
 
+    # per-integration times (synchronised one by one) for the median
+    per = []
+    for i in range(max(args.steps, 10)):
+        ta = time.perf_counter()
+        ctx.integrate(P, functional)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - ta) * 1e3)
+    ms_warm_med = float(np.median(per))
+
+    # warm with Phi kept between integrations (one-wave plans only)
+    ctx.set_phi_cache(True)
+    ctx.integrate(P, functional)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.integrate(P, functional)
+    torch.cuda.synchronize()
+    ms_cache = (time.perf_counter() - t2) * 1e3 / args.steps
+    ENc = ctx.EN.cpu().numpy()
+    ctx.set_phi_cache(False)
+    log(f"warm, Phi cached: {ms_cache:.1f} ms/step")
+    nb_hist = nb_histogram(ctx, w)
+
     # mixed precision: FP32 collocation and contractions, FP64 functional/sums
     mixed = {}
     for prec in args.mixed.split(",") if args.mixed else []:
@@ -316,7 +355,17 @@ def main():
                    "batch_merge": args.batch_merge,
                    "step": "grid build + weights + batching + screening + integration"},
         "warm": {"value": n_nom / (ms_warm * 1e-3), "ms_per_step": ms_warm,
-                 "step": "integration with the grid reused"},
+                 "step": "integration with the grid reused",
+                 "median_ms_single": ms_warm_med, "single_runs": len(per),
+                 "phi_cache": {"value": n_nom / (ms_cache * 1e-3), "ms_per_step": ms_cache,
+                               "active": st["n_waves"] == 1,
+                               "same_E_N": bool(np.array_equal(ENc, EN))}},
+        "nb_histogram_point_weighted": nb_hist,
+        "ssf": {"points_per_s": n_nom / (phase_ms["weights"] * 1e-3),
+                "pair_terms_plain_equiv_per_s":
+                    n_nom * w.natoms * (w.natoms - 1) / (phase_ms["weights"] * 1e-3),
+                "note": "nominal points, and the N_A (N_A - 1) pair terms per point "
+                        "of the plain partition formula, per second of the weights phase"},
         "phase_ms_per_step": phase_ms,
         "mixed": mixed,
         "contractions_tflops": both,

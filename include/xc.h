@@ -252,6 +252,20 @@ int xc_context_export_batches(xc_context* ctx, long long* point_ptr,
                               double* bbox, long long* shell_ptr, int* shells);
 
 /*
+ * Keep the collocation matrices between integrations (enable != 0), for
+ * SCF iterations that integrate many density matrices on one grid: the
+ * matrices Phi^j of the batch-local quantities (Sec. 2.2, Alg. 4) depend on
+ * the grid and the basis only, not on P. When the wave plan has a single
+ * wave, the wave scratch still holds Phi after an integration, and the next
+ * integration that stores Phi in the same type (FP64 for XC_FP64 and
+ * XC_MIXED_FP32_V, FP32 for XC_MIXED_FP32 and XC_MIXED_BF16X3) skips the
+ * collocation kernel; the results are bitwise the same. Costs no device
+ * memory. A grid rebuild, a change of the Phi type or enable = 0 drops the
+ * cached matrices; a plan with several waves never caches. Default off.
+ */
+int xc_context_set_phi_cache(xc_context* ctx, int enable);
+
+/*
  * Turn per-phase timing on (enable != 0) or off; either way the accumulated
  * times are reset. While on, every launch is bracketed by two events on the
  * context's stream.

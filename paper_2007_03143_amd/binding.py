@@ -144,6 +144,8 @@ def _load():
                                               POINTER(c_int)]
     lib.xc_context_set_timing.restype = c_int
     lib.xc_context_set_timing.argtypes = [c_void_p, c_int]
+    lib.xc_context_set_phi_cache.restype = c_int
+    lib.xc_context_set_phi_cache.argtypes = [c_void_p, c_int]
     lib.xc_context_timing.restype = c_int
     lib.xc_context_timing.argtypes = [c_void_p, POINTER(XcTiming)]
     lib.xc_context_destroy.restype = c_int
@@ -292,6 +294,10 @@ def xc_context_set_timing(handle, enable):
     _check(LIB.xc_context_set_timing(handle, 1 if enable else 0))
 
 
+def xc_context_set_phi_cache(handle, enable):
+    _check(LIB.xc_context_set_phi_cache(handle, 1 if enable else 0))
+
+
 def xc_context_timing(handle):
     t = XcTiming()
     _check(LIB.xc_context_timing(handle, byref(t)))
@@ -385,6 +391,9 @@ class XcContext:
 
     def set_timing(self, enable):
         xc_context_set_timing(self.handle, enable)
+
+    def set_phi_cache(self, enable):
+        xc_context_set_phi_cache(self.handle, enable)
 
     def timing(self):
         return xc_context_timing(self.handle)

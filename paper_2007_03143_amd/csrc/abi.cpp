@@ -227,6 +227,7 @@ static void release_all(xc_context* c) {
 // gradient, or Z, plus density partials) fits the budget (Alg. 2: subsets
 // that saturate device memory), and build each wave's tile tables.
 static int plan_waves(xc_context* c) {
+    c->phi_cached_bytes = 0;
     c->waves.clear();
     c->h_wb.clear();
     std::vector<int> gpre, spre;
@@ -315,6 +316,7 @@ static int plan_waves(xc_context* c) {
 
 int build_grid(xc_context* c) {
     c->built = false;
+    c->phi_cached_bytes = 0;
     const long long npa = (long long)c->n_rad * c->n_ang;
     c->n_nominal = npa * (long long)c->gatoms.size();
     if (c->n_nominal == 0) {
@@ -561,6 +563,14 @@ int xc_context_set_timing(xc_context* c, int enable) {
         c->timer.ms[p] = 0.0;
         c->timer.launches[p] = 0;
     }
+    return XC_OK;
+}
+
+int xc_context_set_phi_cache(xc_context* c, int enable) {
+    g_last_error.clear();
+    if (!c) return fail(XC_ERR_INVALID_ARG, "null context");
+    c->phi_cache = enable != 0;
+    if (!c->phi_cache) c->phi_cached_bytes = 0;
     return XC_OK;
 }
 

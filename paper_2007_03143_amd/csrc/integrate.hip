@@ -1177,8 +1177,9 @@ __global__ void k_reduce_en(const double* epart, const double* npart, long long 
 template <bool GGA, typename T, typename TZ>
 static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                          const int* gpre, const int* spre, int count, int gemm_tiles,
-                         int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap) {
-    {
+                         int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
+                         bool colloc) {
+    if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
         hipLaunchKernelGGL((k_colloc<T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
@@ -1213,8 +1214,9 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
 template <bool GGA>
 static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                             const int* gpre, const int* spre, int count, int gemm_tiles,
-                            int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap) {
-    {
+                            int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
+                            bool colloc) {
+    if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
         hipLaunchKernelGGL((k_colloc<float>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
@@ -1248,30 +1250,26 @@ static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre, int count,
                 int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch,
-                int* d_tmap_i) {
+                int* d_tmap_i, bool colloc) {
     if (count == 0) return XC_OK;
-    int2* d_tmap = (int2*)d_tmap_i;
+    int2* t = (int2*)d_tmap_i;
+#define XC_WAVE_ARGS timer, s, d_wb, d_gpre, d_spre, count, gemm_tiles, syr_tiles, d_reqs, \
+                     scratch, t, colloc
     if (precision == XC_MIXED_FP32)
-        return gga ? launch_wave_t<true, float, float>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                       gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap)
-                   : launch_wave_t<false, float, float>(timer, s, d_wb, d_gpre, d_spre,
-                                                        count, gemm_tiles, syr_tiles, d_reqs,
-                                                        scratch, d_tmap);
+        return gga ? launch_wave_t<true, float, float>(XC_WAVE_ARGS)
+                   : launch_wave_t<false, float, float>(XC_WAVE_ARGS);
     if (precision == XC_MIXED_BF16X3)
-        return gga ? launch_wave_bf16<true>(timer, s, d_wb, d_gpre, d_spre, count, gemm_tiles,
-                                            syr_tiles, d_reqs, scratch, d_tmap)
-                   : launch_wave_bf16<false>(timer, s, d_wb, d_gpre, d_spre, count,
-                                             gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap);
+        return gga ? launch_wave_bf16<true>(XC_WAVE_ARGS) : launch_wave_bf16<false>(XC_WAVE_ARGS);
     if (precision == XC_MIXED_FP32_V)
-        return gga ? launch_wave_t<true, double, float>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                        gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap)
-                   : launch_wave_t<false, double, float>(timer, s, d_wb, d_gpre, d_spre,
-                                                         count, gemm_tiles, syr_tiles, d_reqs,
-                                                         scratch, d_tmap);
-    return gga ? launch_wave_t<true, double, double>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                     gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap)
-               : launch_wave_t<false, double, double>(timer, s, d_wb, d_gpre, d_spre, count,
-                                                      gemm_tiles, syr_tiles, d_reqs, scratch, d_tmap);
+        return gga ? launch_wave_t<true, double, float>(XC_WAVE_ARGS)
+                   : launch_wave_t<false, double, float>(XC_WAVE_ARGS);
+    return gga ? launch_wave_t<true, double, double>(XC_WAVE_ARGS)
+               : launch_wave_t<false, double, double>(XC_WAVE_ARGS);
+#undef XC_WAVE_ARGS
+}
+
+int phi_elem_bytes(int precision) {
+    return (precision == XC_MIXED_FP32 || precision == XC_MIXED_BF16X3) ? 4 : 8;
 }
 
 int launch_finish(PhaseTimer* timer, hipStream_t s, double* dV, int nbf,
@@ -1333,11 +1331,19 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
     const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
     const int* gpre = (const int*)c->d_gemm_pre.p;
     const int* spre = (const int*)c->d_syr_pre.p;
+    // With one wave the scratch still holds the previous integration's Phi
+    // (no later kernel writes its slab), so a cached Phi of the same storage
+    // type is used as it stands.
+    const int esz = phi_elem_bytes(precision);
+    const bool cacheable = c->phi_cache && !c->external_scratch && c->waves.size() == 1;
+    const bool colloc = !(cacheable && c->phi_cached_bytes == esz);
+    c->phi_cached_bytes = 0;
     for (const Wave& w : c->waves)
         XC_TRY(launch_wave(&c->timer, c->stream, gga, precision, wb + w.wb_off,
                            gpre + w.pre_off, spre + w.pre_off, w.count, w.gemm_tiles,
                            w.syr_tiles, (const ReqDev*)c->d_req.p, (char*)c->scratch.p,
-                           (int*)c->d_tmap.p));
+                           (int*)c->d_tmap.p, colloc));
+    if (cacheable) c->phi_cached_bytes = esz;
     return launch_finish(&c->timer, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);
 }

@@ -182,6 +182,8 @@ struct xc_context {
     xc::DevBuf epart, npart;
     xc::DevBuf d_req;            // one ReqDev for the context's own integrations
     bool external_scratch = false;  // wave scratch supplied by an engine
+    bool phi_cache = false;         // keep Phi in the scratch between integrations
+    int phi_cached_bytes = 0;       // element size of the Phi the scratch holds; 0: none
 
     xc::PhaseTimer timer;
 
@@ -235,10 +237,14 @@ ReqDev make_req(const xc_context* c, const double* dP, double* dV);
 // The four per-wave launches (collocation, density, functional + Z,
 // potential) over count batches whose descriptors are already on the device.
 // d_tmap: room for 2 * max(gemm_tiles, syr_tiles) ints (tile -> batch map).
+// colloc = false skips the collocation kernel: the scratch already holds Phi
+// of these batches in the storage type of this precision.
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre,
                 int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
-                char* scratch, int* d_tmap);
+                char* scratch, int* d_tmap, bool colloc = true);
+// Bytes per element of the stored Phi under a precision code.
+int phi_elem_bytes(int precision);
 // Fill n doubles with v (a kernel, so it can be captured in a graph).
 int launch_fill(hipStream_t s, double* p, long long n, double v);
 // V mirror and the fixed-order E_xc / N_e sums of one finished integration.

@@ -269,3 +269,67 @@ def test_mixed_fp32_potential_error_vs_oracle(functional):
     assert abs(E - Eo) <= TOL_E and abs(N - No) <= TOL_E
     assert np.abs(V - Vo).max() <= 1e-4
     assert np.array_equal(V, V.T)
+
+
+def test_phi_cache_bitwise_and_invalidation():
+    """Keeping Phi between integrations (one wave) gives the same E, N and V
+    as recomputing it, across density matrices, functionals and the Phi
+    storage types, and collocation runs only when the cached Phi cannot
+    serve (first call, a change of storage type, a grid rebuild, several
+    waves)."""
+    import torch
+    from paper_2007_03143_amd import XcContext
+    w = cfg_water_cluster(n_waters=4, n_rad=30, n_ang=110)
+    rng = np.random.default_rng(11)
+    d = rng.normal(size=w.P.shape)
+    P1 = w.P + 1e-3 * (d + d.T) / np.linalg.norm(d + d.T)
+    Ps = [torch.from_numpy(np.ascontiguousarray(P)).cuda() for P in (w.P, P1)]
+    calls = [(0, "pbe", "fp64"), (1, "pbe", "fp64"), (0, "lda", "fp64"),
+             (1, "pbe", "fp32"), (0, "pbe", "bf16x3"), (1, "pbe", "fp32v"),
+             (0, "lda", "fp64")]
+    g = grid_spec_dict(w)
+    ref = XcContext(w.coords, w.mk_alpha, w.basis, g)
+    cached = XcContext(w.coords, w.mk_alpha, w.basis, g)
+    multi = XcContext(w.coords, w.mk_alpha, w.basis, g, wave_bytes=4 << 20)
+    try:
+        for c in (ref, cached, multi):
+            c.build_grid()
+            c.set_timing(True)
+        cached.set_phi_cache(True)
+        multi.set_phi_cache(True)
+        nw = multi.stats()["n_waves"]
+        assert cached.stats()["n_waves"] == 1 and nw > 1
+
+        def run(c, k, f, p):
+            V, EN = c.integrate(Ps[k], f, p)
+            torch.cuda.synchronize()
+            return EN.cpu().numpy().copy(), V.cpu().numpy().copy()
+
+        for k, f, p in calls:
+            say(f"case phi cache: P{k} {f} {p}")
+            en0, V0 = run(ref, k, f, p)
+            en1, V1 = run(cached, k, f, p)
+            en2, V2 = run(multi, k, f, p)
+            tol = 1e-14 * np.abs(V0).max()
+            assert np.array_equal(en0, en1), (en0, en1)
+            assert np.abs(V1 - V0).max() <= tol
+            assert np.abs(en2 - en0).max() <= 1e-12 * np.abs(en0).max()
+            assert np.abs(V2 - V0).max() <= 1e-12 * np.abs(V0).max()
+        # Phi types by call: 8 8 8 4 4 8 8 -> collocation at calls 1, 4, 6
+        assert ref.timing()["colloc"]["launches"] == len(calls)
+        assert cached.timing()["colloc"]["launches"] == 3
+        assert multi.timing()["colloc"]["launches"] == len(calls) * nw
+        # a rebuild drops the cache; switching it off drops it too
+        cached.build_grid()
+        cached.set_timing(True)
+        en1, V1 = run(cached, 0, "pbe", "fp64")
+        en1b, _ = run(cached, 0, "pbe", "fp64")
+        cached.set_phi_cache(False)
+        en1c, _ = run(cached, 0, "pbe", "fp64")
+        assert cached.timing()["colloc"]["launches"] == 2
+        en0, V0 = run(ref, 0, "pbe", "fp64")
+        assert np.array_equal(en0, en1) and np.array_equal(en0, en1b)
+        assert np.array_equal(en0, en1c)
+    finally:
+        for c in (ref, cached, multi):
+            c.close()

@@ -115,7 +115,7 @@ void release_build_temporaries(xc_context* c) {
 
 size_t device_bytes(const xc_context* c) {
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn, &c->d_nbr_idx, &c->d_nbr_R,
+                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R,
                             &c->raw_x, &c->raw_y,
                             &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                             &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
@@ -210,7 +210,7 @@ static int check_func_prec(int functional, int precision) {
 
 static void release_all(xc_context* c) {
     DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_flmn, &c->d_nbr_idx, &c->d_nbr_R,
+                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R,
                       &c->raw_x, &c->raw_y,
                       &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                       &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
@@ -405,15 +405,9 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
         ff += ncart(basis->shell_L[s]);
     }
     c->nbf = ff;
-    std::vector<int> fshell, flmn;
-    for (int s2 = 0; s2 < c->nshells; ++s2) {
-        const int L = basis->shell_L[s2];
-        for (int l = L; l >= 0; --l)
-            for (int m = L - l; m >= 0; --m) {
-                fshell.push_back(s2);
-                flmn.push_back(l | (m << 4) | ((L - l - m) << 8));
-            }
-    }
+    std::vector<int> fshell;
+    for (int s2 = 0; s2 < c->nshells; ++s2)
+        for (int k = 0; k < ncart(basis->shell_L[s2]); ++k) fshell.push_back(s2);
     c->prim_alpha.assign(basis->prim_alpha, basis->prim_alpha + po);
     c->prim_coef.assign(basis->prim_coef, basis->prim_coef + po);
     c->n_rad = g->n_rad;
@@ -439,7 +433,6 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
     if (rc == XC_OK) rc = upload(c->d_shells, sh.data(), sizeof(ShellDev) * sh.size(), c->stream);
     if (rc == XC_OK) rc = upload(c->d_palpha, c->prim_alpha.data(), 8 * (size_t)po, c->stream);
     if (rc == XC_OK) rc = upload(c->d_fshell, fshell.data(), sizeof(int) * fshell.size(), c->stream);
-    if (rc == XC_OK) rc = upload(c->d_flmn, flmn.data(), sizeof(int) * flmn.size(), c->stream);
     if (rc == XC_OK) rc = upload(c->d_pcoef, c->prim_coef.data(), 8 * (size_t)po, c->stream);
     if (rc == XC_OK) rc = upload(c->d_ang, c->ang.data(), 8 * c->ang.size(), c->stream);
     if (rc == XC_OK) {
@@ -496,7 +489,7 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
     size_t pers = 0;
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells,
                             &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
-                            &c->d_fshell, &c->d_flmn, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
+                            &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->epart,
                             &c->npart};

@@ -345,8 +345,6 @@ int run_batching(xc_context* c, const std::vector<long long>& atom_kept) {
 }
 
 // ------------------------------------------------------------ screening ---
-__device__ inline int ncart(int L) { return (L + 1) * (L + 2) / 2; }
-
 // Alg. 1 with the closed-ball reading: the sphere (R, r_cut) meets the box
 // [lo, hi] when r_cut^2 minus the squared distance from R to the box is >= 0.
 __device__ inline bool shell_meets_box(const ShellDev& s, const Cell& b) {

@@ -52,6 +52,18 @@ __device__ inline double block_sum_256(double v, double* smem) {
 // Workgroups are dispatched round-robin over the 8 XCDs; this maps the
 // hardware block id to a logical id so that consecutive logical ids run on
 // the same XCD and share its L2.
+// Value of v on lane l of the wave (l wave-uniform). The register is read
+// even where lane l is inactive, so v must have been written there.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cartesian functions of a shell of angular momentum L.
+__device__ inline int ncart(int L) { return (L + 1) * (L + 2) / 2; }
+
 __device__ inline int xcd_remap(int bid, int nblk) {
     const int xcd = bid & 7, idx = bid >> 3;
     const int base = nblk >> 3, rem = nblk & 7;

@@ -54,7 +54,7 @@ template <> struct Mfma<float> {
 struct ReqG {
     gptr<const ShellDev> shells;
     gptr<const double> palpha, pcoef;
-    gptr<const int> shell_list, shell_loff, func_list, func_shell, func_lmn;
+    gptr<const int> shell_list, shell_loff, func_list, func_shell;
     gptr<const double> px, py, pz, pw, P;
     gptr<double> V, epart, npart;
     double rho_thresh;
@@ -70,7 +70,6 @@ __device__ inline ReqG global_view(const ReqDev& r) {
     g.shell_loff = to_global(r.shell_loff);
     g.func_list = to_global(r.func_list);
     g.func_shell = to_global(r.func_shell);
-    g.func_lmn = to_global(r.func_lmn);
     g.px = to_global(r.px);
     g.py = to_global(r.py);
     g.pz = to_global(r.pz);
@@ -115,29 +114,8 @@ __device__ inline void shell_radial(const ShellDev& sh, gptr<const double> palph
     }
 }
 
-// The same for a shell that is the same on every lane of the wave, with a
-// primitive skipped when alpha r2 >= 746 on every lane: its exponential is
-// then exactly zero in FP64 everywhere, so the sums are the same bit for bit
-// (tight primitives far from their centre, the common case in the density
-// epilogue), and the wave-wide test keeps the lanes together.
+// alpha r2 at and beyond which e^{-alpha r2} is exactly zero in FP64.
 constexpr double kExpZero = 746.0;
-
-__device__ inline void shell_radial_wave(const ShellDev& sh, gptr<const double> palpha,
-                                         gptr<const double> pcoef, double r2, double& rad,
-                                         double& drad) {
-    rad = 0.0;
-    drad = 0.0;
-    const bool in = r2 <= sh.rcut2;
-    for (int p = 0; p < sh.nprim; ++p) {
-        const double a = palpha[sh.prim_off + p];
-        const double x = a * r2;
-        if (__any(in && x < kExpZero)) {
-            const double de = in ? pcoef[sh.prim_off + p] * exp(-x) : 0.0;
-            rad += de;
-            drad -= 2.0 * a * de;
-        }
-    }
-}
 
 // Squared distance with the same rounding in every kernel (no contraction),
 // so the cutoff test gives the same answer wherever it is evaluated.
@@ -231,7 +209,8 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
     // zero the padding rows n_b .. n_bp - 1
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) Phi[(size_t)B.nb * B.ngp + k] = T(0);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     for (int sl = wave; sl < B.nshell; sl += 4) {
         const int s = R.shell_list[B.shell_off + sl];
         const int loff = R.shell_loff[B.shell_off + sl];
@@ -252,57 +231,117 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
     }
 }
 
+// Radial part of a shell that is the same on every lane of the wave. A
+// primitive is skipped when alpha r2 >= kExpZero on every lane: its
+// exponential is then zero everywhere, so the sums are the same bit for bit
+// (tight primitives far from their centre, the common case here), and the
+// wave-wide test keeps the lanes together. `in` is false on lanes without a
+// point.
+__device__ inline void shell_radial_wave(const ShellDev& sh, gptr<const double> palpha,
+                                         gptr<const double> pcoef, double r2, bool in,
+                                         double& rad, double& drad) {
+    rad = 0.0;
+    drad = 0.0;
+    in = in && r2 <= sh.rcut2;
+    for (int p = 0; p < sh.nprim; ++p) {
+        const double a = palpha[sh.prim_off + p];
+        const double x = a * r2;
+        if (__any(in && x < kExpZero)) {
+            const double de = in ? pcoef[sh.prim_off + p] * exp(-x) : 0.0;
+            rad += de;
+            drad -= 2.0 * a * de;
+        }
+    }
+}
+
+// Contributions of the components k0 .. k0 + cnt - 1 of one shell (tile
+// rows rl .. rl + cnt - 1; all wave-uniform) at one point: phi*X and, for
+// GGA, grad phi*X, with the Cartesian exponents known at compile time. The
+// X values are read first, all at once.
+template <int L, bool GGA>
+__device__ inline void rho_shell(int k0, int cnt, double dx, double dy, double dz, double rad,
+                                 double drad, const double (*Xs)[kTile + 1], int rl, int c,
+                                 double (&q)[4]) {
+    constexpr int NC = (L + 1) * (L + 2) / 2;
+    double xv[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const double v = Xs[min(max(rl + k - k0, 0), kTile - 1)][c];
+        xv[k] = (k >= k0 && k < k0 + cnt) ? v : 0.0;
+    }
+    double xp[L + 1], yp[L + 1], zp[L + 1];
+    xp[0] = yp[0] = zp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        xp[k] = xp[k - 1] * dx;
+        yp[k] = yp[k - 1] * dy;
+        zp[k] = zp[k - 1] * dz;
+    }
+    int comp = 0;
+#pragma unroll
+    for (int l = L; l >= 0; --l) {
+#pragma unroll
+        for (int m = L - l; m >= 0; --m) {
+            const int n = L - l - m;
+            if (comp >= k0 && comp < k0 + cnt) {
+                const double ang = xp[l] * yp[m] * zp[n];
+                q[0] += ang * rad * xv[comp];
+                if (GGA) {
+                    const double ad = ang * drad;
+                    double gx = ad * dx, gy = ad * dy, gz = ad * dz;
+                    if (l > 0) gx += l * xp[l - 1] * yp[m] * zp[n] * rad;
+                    if (m > 0) gy += m * xp[l] * yp[m - 1] * zp[n] * rad;
+                    if (n > 0) gz += n * xp[l] * yp[m] * zp[n - 1] * rad;
+                    q[1] += gx * xv[comp];
+                    q[2] += gy * xv[comp];
+                    q[3] += gz * xv[comp];
+                }
+            }
+            ++comp;
+        }
+    }
+}
+
 // Epilogue of the density contraction: the X tile (64 functions x 64
-// points, FP64) is in LDS. Each thread takes one point and 16 consecutive
-// functions (one row group per wave), re-evaluates phi (and grad phi) from
-// the shell data in FP64 and reduces phi*X (grad phi * X) into the per-row-
-// tile partials part[mt][q][point], q = rho, dx, dy, dz.
+// points, FP64) is in LDS. Each thread takes one point and the 16
+// consecutive functions of its wave, walks them shell by shell (the rows of
+// a shell are consecutive components of it), re-evaluates the radial part
+// once per shell and phi (and grad phi) per component in FP64, and reduces
+// phi*X (grad phi * X) into the per-row-tile partials part[mt][q][point],
+// q = rho, dx, dy, dz. All lanes take part; a lane past n_g has no point
+// (zero radial part, and its X column is zero padding).
+// The point's coordinates (x, y, z; has = false past n_g) are loaded by the
+// caller before its main loop, so their latency is hidden.
 template <bool GGA>
 __device__ inline void rho_epilogue(const WaveBatch& B, const ReqG& R, int m0, int n0, int mt,
-                                    double (*Xs)[kTile + 1], const int* fsh, const int* flmn,
-                                    char* scratch) {
-    const int tid = threadIdx.x;
-    const int c = tid & 63, g = tid >> 6;
-    const int col = n0 + c;
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-    if (col < B.ng) {
-        const double x = R.px[B.pt_off + col], y = R.py[B.pt_off + col],
-                     z = R.pz[B.pt_off + col];
-        int prev = -1;
-        double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
-        for (int rr = 0; rr < 16; ++rr) {
-            const int rl = g * 16 + rr;
-            if (m0 + rl >= B.nb) break;
-            // one row group per wave: the shell is wave-uniform
-            const int sidx = __builtin_amdgcn_readfirstlane(fsh[rl]);
-            if (sidx != prev) {
-                const ShellDev sh = load_shell(R.shells + sidx);
-                const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
-                shell_radial_wave(sh, R.palpha, R.pcoef, r2, rad, drad);
-                prev = sidx;
-            }
-            const int lmn = flmn[rl];
-            const double xv = Xs[rl][c];
-            if (GGA) {
-                double v, gx, gy, gz;
-                cart_eval(lmn & 15, (lmn >> 4) & 15, lmn >> 8, dx, dy, dz, rad, drad, v, gx,
-                          gy, gz);
-                q0 += v * xv;
-                q1 += gx * xv;
-                q2 += gy * xv;
-                q3 += gz * xv;
-            } else {
-                q0 += ipow3(dx, lmn & 15) * ipow3(dy, (lmn >> 4) & 15) *
-                      ipow3(dz, lmn >> 8) * rad * xv;
-            }
+                                    double (*Xs)[kTile + 1], const int* fsh, const int* frow,
+                                    double x, double y, double z, bool has, char* scratch) {
+    const int c = threadIdx.x & 63;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    const int rend = min(g * 16 + 16, B.nb - m0);
+    for (int rl = g * 16; rl < rend;) {
+        const int sidx = __builtin_amdgcn_readfirstlane(fsh[rl]);
+        const ShellDev sh = load_shell(R.shells + sidx);
+        const int nc = ncart(sh.L);
+        const int k0 = min(max(__builtin_amdgcn_readfirstlane(frow[rl]) - sh.first_func, 0),
+                           nc - 1);
+        const int cnt = min(nc - k0, rend - rl);
+        double dx, dy, dz, rad, drad;
+        const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
+        shell_radial_wave(sh, R.palpha, R.pcoef, r2, has, rad, drad);
+        switch (sh.L) {
+            case 0: rho_shell<0, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+            case 1: rho_shell<1, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+            case 2: rho_shell<2, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+            default: rho_shell<3, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
         }
+        rl += cnt;
     }
     __syncthreads();
     double* red = &Xs[0][0];
-    red[(g * 4 + 0) * kTile + c] = q0;
-    red[(g * 4 + 1) * kTile + c] = q1;
-    red[(g * 4 + 2) * kTile + c] = q2;
-    red[(g * 4 + 3) * kTile + c] = q3;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) red[(g * 4 + qq) * kTile + c] = q[qq];
     __syncthreads();
     if (g == 0) {
         double* part = (double*)(scratch + 8 * B.part_off);
@@ -343,6 +382,15 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int m0 = mt * kTile, n0 = nt * kTile;
     const T* Phi = (const T*)(scratch + 8 * B.phi_off);
     const gptr<const int> fl = func_list + B.func_off;
+    // the epilogue's point (one per lane), loaded now so that its latency hides
+    const bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    if (has) {
+        const long long pi = B.pt_off + n0 + (threadIdx.x & 63);
+        ex = R.px[pi];
+        ey = R.py[pi];
+        ez = R.pz[pi];
+    }
 
     // operand tiles during the main loop, the X tile in the epilogue
     constexpr int kABytes = 2 * kTile * 17 * (int)sizeof(T);
@@ -353,11 +401,12 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     T (*As)[kTile][17] = reinterpret_cast<T (*)[kTile][17]>(lds);
     T (*Bs)[16][kTile + 1] = reinterpret_cast<T (*)[16][kTile + 1]>(lds + kABytes);
     double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
-    __shared__ int frow[kTile], fsh[kTile], flmn[kTile];
+    __shared__ int frow[kTile], fsh[kTile];
     // function indices (columns of P) of four consecutive K steps
     __shared__ __attribute__((aligned(16))) int sfl[4][16];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const int wm = wave >> 1, wn = wave & 1;
     const int nk = B.nbp / 16;
     // The 16 column indices of a K step are loaded once, by threads 0-15,
@@ -380,7 +429,6 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         const int f = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
         frow[tid] = f;
         fsh[tid] = f >= 0 ? R.func_shell[f] : 0;
-        flmn[tid] = f >= 0 ? R.func_lmn[f] : 0;
     }
     __syncthreads();
 
@@ -504,7 +552,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
                     double(acc[mb][nb][r]);
     __syncthreads();
 
-    rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, flmn, scratch);
+    rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, frow, ex, ey, ez, has, scratch);
 }
 
 // ------------------------------------------------- functional + Z matrix --
@@ -574,7 +622,8 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
     T* Zm = (T*)(scratch + 8 * (B.phi_off + (long long)B.nbp * B.ngp));
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) Zm[(size_t)B.nb * B.ngp + k] = T(0);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     for (int sl = wave; sl < B.nshell; sl += 4) {
         const int sidx = R.shell_list[B.shell_off + sl];
         const int loff = R.shell_loff[B.shell_off + sl];
@@ -640,7 +689,8 @@ __global__ __launch_bounds__(256) void k_syr2k(
     // global function indices of the tile's rows and columns (-1: padding)
     __shared__ int sfI[kTile], sfJ[kTile];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     if (tid < kTile) {
         const int r = I * kTile + tid;
         sfI[tid] = r < B.nb ? fl[r] : -1;
@@ -824,6 +874,15 @@ __global__ __launch_bounds__(256) void k_gemm_rho_bf16(
     const int m0 = mt * kTile, n0 = nt * kTile;
     const float* Phi = (const float*)(scratch + 8 * B.phi_off);
     const gptr<const int> fl = R.func_list + B.func_off;
+    // the epilogue's point (one per lane), loaded now so that its latency hides
+    const bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    if (has) {
+        const long long pi = B.pt_off + n0 + (threadIdx.x & 63);
+        ex = R.px[pi];
+        ey = R.py[pi];
+        ez = R.pz[pi];
+    }
 
     // four operand tiles (A, B) x (hi, lo), double-buffered; X in the epilogue
     constexpr int kOpBytes = kTile * kBP * 2;
@@ -834,10 +893,11 @@ __global__ __launch_bounds__(256) void k_gemm_rho_bf16(
         return reinterpret_cast<__bf16 (*)[kBP]>(lds + (which * 2 + buf) * kOpBytes);
     };
     double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
-    __shared__ int frow[kTile], fsh[kTile], flmn[kTile];
+    __shared__ int frow[kTile], fsh[kTile];
     __shared__ __attribute__((aligned(16))) int sfl[2][kKB];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const int wm = wave >> 1, wn = wave & 1;
     const int nk = (B.nbp + kKB - 1) / kKB;
     int fnext = -1;
@@ -860,7 +920,6 @@ __global__ __launch_bounds__(256) void k_gemm_rho_bf16(
         const int f = (m0 + tid < B.nb) ? fl[m0 + tid] : -1;
         frow[tid] = f;
         fsh[tid] = f >= 0 ? R.func_shell[f] : 0;
-        flmn[tid] = f >= 0 ? R.func_lmn[f] : 0;
     }
     __syncthreads();
 
@@ -969,7 +1028,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho_bf16(
                 Xs[wm * 32 + mb * 16 + 4 * (lane >> 4) + r][wn * 32 + nb * 16 + (lane & 15)] =
                     double(acc[mb][nb][r]);
     __syncthreads();
-    rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, flmn, scratch);
+    rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, frow, ex, ey, ez, has, scratch);
 }
 
 // Potential contraction V^j = Z Phi^T + Phi Z^T in split BF16 (Phi and Z
@@ -1003,7 +1062,8 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     };
     __shared__ int sfI[kTile], sfJ[kTile];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     if (tid < kTile) {
         const int r = I * kTile + tid;
         sfI[tid] = r < B.nb ? fl[r] : -1;
@@ -1311,7 +1371,6 @@ ReqDev make_req(const xc_context* c, const double* dP, double* dV) {
     r.epart = (double*)c->epart.p;
     r.npart = (double*)c->npart.p;
     r.func_shell = (const int*)c->d_fshell.p;
-    r.func_lmn = (const int*)c->d_flmn.p;
     r.rho_thresh = c->rho_thresh;
     r.nbf = c->nbf;
     return r;

@@ -91,7 +91,6 @@ struct ReqDev {
     const int* shell_loff;
     const int* func_list;
     const int* func_shell;   // global shell of every global function
-    const int* func_lmn;     // its Cartesian exponents, l | m << 4 | n << 8
     const double* px;
     const double* py;
     const double* pz;
@@ -154,7 +153,7 @@ struct xc_context {
 
     // device inputs
     xc::DevBuf d_atoms, d_invR, d_nnhalf, d_shells, d_palpha, d_pcoef, d_ang, d_gatoms;
-    xc::DevBuf d_fshell, d_flmn;
+    xc::DevBuf d_fshell;
     xc::DevBuf d_nbr_idx, d_nbr_R;  // per atom: all atoms by distance
 
     // grid and batches

@@ -128,38 +128,38 @@ __device__ inline double dist2_nc(double x, double y, double z, const ShellDev& 
     return dx * dx + dy * dy + dz * dz;
 }
 
-__device__ inline double ipow3(double x, int n) {
-    return n == 0 ? 1.0 : (n == 1 ? x : (n == 2 ? x * x : x * x * x));
-}
-
-// Value and gradient of x^l y^m z^n rad(r^2) (eq. gau_cart).
-__device__ inline void cart_eval(int l, int m, int n, double dx, double dy, double dz,
-                                 double rad, double drad, double& v, double& gx,
-                                 double& gy, double& gz) {
-    const double xl = ipow3(dx, l), ym = ipow3(dy, m), zn = ipow3(dz, n);
-    const double ang = xl * ym * zn;
-    v = ang * rad;
-    const double ad = ang * drad;
-    gx = (l ? l * ipow3(dx, l - 1) * ym * zn : 0.0) * rad + ad * dx;
-    gy = (m ? m * xl * ipow3(dy, m - 1) * zn : 0.0) * rad + ad * dy;
-    gz = (n ? n * xl * ym * ipow3(dz, n - 1) : 0.0) * rad + ad * dz;
-}
-
 // Z entries of the (L+1)(L+2)/2 functions of one shell at one point:
-// z = a phi + b . grad phi, written down the rows starting at out.
+// z = a phi + b . grad phi, written down the rows starting at out. With
+// phi = A(d) rad and grad phi = grad A rad + A drad d (eq. gau_cart: A the
+// Cartesian monomial, d the displacement from the centre), z = A (a rad + drad b.d) + rad b.grad A, so
+// the shell-wide factors are formed once and each component costs a few
+// products with its exponents known at compile time.
 template <int L, typename T>
 __device__ inline void z_shell(double dx, double dy, double dz, double rad, double drad,
                                double a, double bx, double by, double bz, T* out,
                                int ngp) {
+    double xp[L + 1], yp[L + 1], zp[L + 1];
+    xp[0] = yp[0] = zp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        xp[k] = xp[k - 1] * dx;
+        yp[k] = yp[k - 1] * dy;
+        zp[k] = zp[k - 1] * dz;
+    }
+    const double t0 = a * rad + (bx * dx + by * dy + bz * dz) * drad;
+    const double rbx = rad * bx, rby = rad * by, rbz = rad * bz;
     int c = 0;
 #pragma unroll
     for (int l = L; l >= 0; --l) {
 #pragma unroll
         for (int m = L - l; m >= 0; --m) {
             const int n = L - l - m;
-            double v, gx, gy, gz;
-            cart_eval(l, m, n, dx, dy, dz, rad, drad, v, gx, gy, gz);
-            out[(size_t)c * ngp] = T(a * v + bx * gx + by * gy + bz * gz);
+            const double yz = yp[m] * zp[n];
+            double z = xp[l] * yz * t0;
+            if (l > 0) z += rbx * (l * xp[l - 1] * yz);
+            if (m > 0) z += rby * (m * xp[l] * yp[m - 1] * zp[n]);
+            if (n > 0) z += rbz * (n * xp[l] * yp[m] * zp[n - 1]);
+            out[(size_t)c * ngp] = T(z);
             ++c;
         }
     }
@@ -256,8 +256,10 @@ __device__ inline void shell_radial_wave(const ShellDev& sh, gptr<const double> 
 
 // Contributions of the components k0 .. k0 + cnt - 1 of one shell (tile
 // rows rl .. rl + cnt - 1; all wave-uniform) at one point: phi*X and, for
-// GGA, grad phi*X, with the Cartesian exponents known at compile time. The
-// X values are read first, all at once.
+// GGA, grad phi*X. With phi = A(d) rad and grad phi = grad A rad + A drad d,
+// the sums over the components need only S = sum X A and the three sums
+// X dA/dx, X dA/dy, X dA/dz, formed with the exponents known at compile
+// time. The X values are read first, all at once.
 template <int L, bool GGA>
 __device__ inline void rho_shell(int k0, int cnt, double dx, double dy, double dz, double rad,
                                  double drad, const double (*Xs)[kTile + 1], int rl, int c,
@@ -277,6 +279,7 @@ __device__ inline void rho_shell(int k0, int cnt, double dx, double dy, double d
         yp[k] = yp[k - 1] * dy;
         zp[k] = zp[k - 1] * dz;
     }
+    double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     int comp = 0;
 #pragma unroll
     for (int l = L; l >= 0; --l) {
@@ -284,21 +287,23 @@ __device__ inline void rho_shell(int k0, int cnt, double dx, double dy, double d
         for (int m = L - l; m >= 0; --m) {
             const int n = L - l - m;
             if (comp >= k0 && comp < k0 + cnt) {
-                const double ang = xp[l] * yp[m] * zp[n];
-                q[0] += ang * rad * xv[comp];
+                const double yz = yp[m] * zp[n];
+                s0 += xv[comp] * (xp[l] * yz);
                 if (GGA) {
-                    const double ad = ang * drad;
-                    double gx = ad * dx, gy = ad * dy, gz = ad * dz;
-                    if (l > 0) gx += l * xp[l - 1] * yp[m] * zp[n] * rad;
-                    if (m > 0) gy += m * xp[l] * yp[m - 1] * zp[n] * rad;
-                    if (n > 0) gz += n * xp[l] * yp[m] * zp[n - 1] * rad;
-                    q[1] += gx * xv[comp];
-                    q[2] += gy * xv[comp];
-                    q[3] += gz * xv[comp];
+                    if (l > 0) sx += xv[comp] * (l * xp[l - 1] * yz);
+                    if (m > 0) sy += xv[comp] * (m * xp[l] * yp[m - 1] * zp[n]);
+                    if (n > 0) sz += xv[comp] * (n * xp[l] * yp[m] * zp[n - 1]);
                 }
             }
             ++comp;
         }
+    }
+    q[0] += rad * s0;
+    if (GGA) {
+        const double ds = drad * s0;
+        q[1] += ds * dx + rad * sx;
+        q[2] += ds * dy + rad * sy;
+        q[3] += ds * dz + rad * sz;
     }
 }
 

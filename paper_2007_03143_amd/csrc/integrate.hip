@@ -629,19 +629,27 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) Zm[(size_t)B.nb * B.ngp + k] = T(0);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    for (int sl = wave; sl < B.nshell; sl += 4) {
-        const int sidx = R.shell_list[B.shell_off + sl];
-        const int loff = R.shell_loff[B.shell_off + sl];
-        const ShellDev sh = load_shell(R.shells + sidx);
-        for (int i = lane; i < B.ngp; i += 64) {
+    // each lane takes a point (its coordinates and Z factors read once), the
+    // wave takes shells wave, wave + 4, ... of the batch's list
+    for (int i = lane; i < B.ngp; i += 64) {
+        const bool hasp = i < B.ng;
+        double px = 0.0, py = 0.0, pz = 0.0;
+        if (hasp) {
+            px = R.px[B.pt_off + i];
+            py = R.py[B.pt_off + i];
+            pz = R.pz[B.pt_off + i];
+        }
+        const double a = sa[i], bx = sbx[i], by = sby[i], bz = sbz[i];
+        for (int sl = wave; sl < B.nshell; sl += 4) {
+            const int sidx = R.shell_list[B.shell_off + sl];
+            const int loff = R.shell_loff[B.shell_off + sl];
+            const ShellDev sh = load_shell(R.shells + sidx);
             double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
-            if (i < B.ng) {
-                const double r2 = dist2_nc(R.px[B.pt_off + i], R.py[B.pt_off + i],
-                                           R.pz[B.pt_off + i], sh, dx, dy, dz);
+            if (hasp) {
+                const double r2 = dist2_nc(px, py, pz, sh, dx, dy, dz);
                 shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
             }
             T* out = Zm + (size_t)loff * B.ngp + i;
-            const double a = sa[i], bx = sbx[i], by = sby[i], bz = sbz[i];
             switch (sh.L) {
                 case 0: z_shell<0, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
                 case 1: z_shell<1, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;

@@ -38,10 +38,22 @@ PHASE_KERNEL = {"density": ("k_gemm_rho", "paper_2007_03143_amd/csrc/integrate.h
                 "potential": ("k_syr2k", "paper_2007_03143_amd/csrc/integrate.hip")}
 
 
+def code_text(src):
+    """C/C++ source with comments removed and each line stripped of
+    surrounding blanks, blank lines dropped: what the compiler sees, so a
+    comment-only edit keeps the hash (string literals holding comment
+    markers are not expected in the kernel sources)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(l.strip() for l in src.splitlines() if l.strip())
+
+
 def source_sha256(rel):
+    """SHA-256 of a kernel source's code text (code_text)."""
     import hashlib
-    with open(os.path.join(HERE, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    with open(os.path.join(HERE, rel), encoding="utf-8") as f:
+        return hashlib.sha256(code_text(f.read()).encode()).hexdigest()
 
 
 def nb_histogram(ctx, w, width=128):

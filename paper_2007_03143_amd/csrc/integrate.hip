@@ -131,9 +131,10 @@ __device__ inline double dist2_nc(double x, double y, double z, const ShellDev& 
 // Z entries of the (L+1)(L+2)/2 functions of one shell at one point:
 // z = a phi + b . grad phi, written down the rows starting at out. With
 // phi = A(d) rad and grad phi = grad A rad + A drad d (eq. gau_cart: A the
-// Cartesian monomial, d the displacement from the centre), z = A (a rad + drad b.d) + rad b.grad A, so
-// the shell-wide factors are formed once and each component costs a few
-// products with its exponents known at compile time.
+// Cartesian monomial, d the displacement from the centre),
+// z = A (a rad + drad b.d) + rad b.grad A, so the shell-wide factors are
+// formed once and each component costs a few products with its exponents
+// known at compile time.
 template <int L, typename T>
 __device__ inline void z_shell(double dx, double dy, double dz, double rad, double drad,
                                double a, double bx, double by, double bz, T* out,
@@ -314,9 +315,9 @@ __device__ inline void rho_shell(int k0, int cnt, double dx, double dy, double d
 // once per shell and phi (and grad phi) per component in FP64, and reduces
 // phi*X (grad phi * X) into the per-row-tile partials part[mt][q][point],
 // q = rho, dx, dy, dz. All lanes take part; a lane past n_g has no point
-// (zero radial part, and its X column is zero padding).
-// The point's coordinates (x, y, z; has = false past n_g) are loaded by the
-// caller before its main loop, so their latency is hidden.
+// (has = false: zero radial part, and its X column is zero padding). The
+// point's coordinates x, y, z are loaded by the caller before its main loop,
+// so their latency is hidden.
 template <bool GGA>
 __device__ inline void rho_epilogue(const WaveBatch& B, const ReqG& R, int m0, int n0, int mt,
                                     double (*Xs)[kTile + 1], const int* fsh, const int* frow,
@@ -363,11 +364,9 @@ __device__ inline void rho_epilogue(const WaveBatch& B, const ReqG& R, int m0, i
 // ------------------------------------------------------- density (GEMM) ----
 // Tile of 64 functions x 64 points of X = P^j Phi^j; 4 waves, each a 32 x 32
 // block of 2 x 2 MFMA 16x16x4 tiles. A operand rows are gathered from the
-// full P through the batch's function list. The epilogue spills X to LDS;
-// then each thread takes one point and 16 consecutive functions (mostly of
-// one or two shells), re-evaluates phi (and grad phi) from the shell data in
-// FP64 and reduces phi*X (grad phi * X) into per-row-tile partials
-// part[mt][q][point], q = rho, dx, dy, dz.
+// full P through the batch's function list. The epilogue (rho_epilogue)
+// spills X to LDS and reduces phi*X (grad phi * X) into per-row-tile
+// partials part[mt][q][point], q = rho, dx, dy, dz.
 template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_gemm_rho(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
@@ -562,8 +561,9 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 
 // ------------------------------------------------- functional + Z matrix --
 // One workgroup per batch: rho, grad rho from the partials, the functional
-// per point, the batch's E_xc and N_e partials, then Z^j (eq. z_mat)
-// re-evaluated shell by shell from the shell data and stored in slab 1.
+// per point, the batch's E_xc and N_e partials, then Z^j (eq. z_mat) from
+// phi and grad phi re-evaluated from the shell data (each lane a point, the
+// wave's shells in turn), stored in slab 1.
 template <bool GGA, typename T>
 __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb,
                                                 const ReqDev* __restrict__ reqs,

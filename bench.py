@@ -196,7 +196,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="water64")
     ap.add_argument("--wave-gb", type=float, default=0.0)
     ap.add_argument("--cpu-stride", type=int, default=2)

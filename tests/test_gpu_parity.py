@@ -333,3 +333,27 @@ def test_phi_cache_bitwise_and_invalidation():
     finally:
         for c in (ref, cached, multi):
             c.close()
+
+
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_one_shot_host_entry_matches_oracle(functional):
+    """xc_integrate with host P and host V (the one-shot entry point: it
+    creates a context on the null stream, copies P in and V out) against the
+    oracle, and equal to the context path's result."""
+    import paper_2007_03143_amd as pkg
+    w = cfg_water(functional)
+    say(f"case one-shot host entry water {functional}")
+    E, N, V = pkg.xc_integrate(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w), functional, w.P)
+    Eo, No, Vo = oracle_integrate(w, functional)
+    say(f"  dE {E - Eo:.3e} dN {N - No:.3e} max dV {np.abs(V - Vo).max():.3e}")
+    assert abs(E - Eo) <= TOL_E and abs(N - No) <= TOL_E
+    assert np.abs(V - Vo).max() <= TOL_V
+    assert np.array_equal(V, V.T)
+    Ec, Nc, Vc, _ = gpu_integrate(w, functional)
+    assert Ec == E and Nc == N
+    assert np.abs(Vc - V).max() <= 1e-14 * np.abs(V).max()
+    # a mixed mode through the same entry
+    E32, N32, V32 = pkg.xc_integrate(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w),
+                                     functional, w.P, "fp32v")
+    assert E32 == E and N32 == N
+    assert np.abs(V32 - Vo).max() <= 1e-4

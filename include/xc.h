@@ -231,6 +231,23 @@ int xc_context_build_grid(xc_context* ctx);
 int xc_context_integrate(xc_context* ctx, int functional, int precision,
                          const double* d_P, double* d_V, double* d_EN);
 
+/*
+ * Device memory of this context's integrations, for admission decisions
+ * (the batch-subset waves of Alg. 2 are planned against a memory budget).
+ *  min_bytes     persistent data (grid, batches, screened lists,
+ *                descriptors, partial sums) plus the wave scratch of the
+ *                largest single batch: the least with which the context can
+ *                integrate (one batch per wave at worst)
+ *  cached_bytes  persistent data plus the scratch of all batches at once:
+ *                a one-wave plan, which also lets xc_context_set_phi_cache
+ *                keep Phi
+ * Exact once the grid is built. Before that only min_bytes is given, as an
+ * estimate from the nominal grid size (build temporaries included) with one
+ * batch bounded by the whole basis; cached_bytes is then 0 (it depends on
+ * the screening). Either pointer may be NULL. No device work.
+ */
+int xc_context_footprint(xc_context* ctx, size_t* min_bytes, size_t* cached_bytes);
+
 /* Sizes of the built grid (host struct, filled synchronously). */
 int xc_context_stats(xc_context* ctx, xc_stats* out);
 

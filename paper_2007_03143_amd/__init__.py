@@ -8,6 +8,7 @@ from .binding import (XcContext, XcError, xc_abi_version, xc_context_build_grid,
                       xc_context_export_batches, xc_context_export_grid,
                       xc_context_integrate, xc_context_stats, xc_integrate,
                       xc_context_set_timing, xc_context_set_phi_cache,
+                      xc_context_footprint,
                       xc_context_timing, PHASES,
                       xc_engine_create, xc_engine_add_request, xc_engine_submit,
                       xc_engine_step, xc_engine_poll, xc_engine_release,
@@ -20,7 +21,7 @@ __all__ = ["XcContext", "XcError", "xc_abi_version", "xc_context_build_grid",
            "xc_context_create", "xc_context_destroy", "xc_context_export_batches",
            "xc_context_export_grid", "xc_context_integrate", "xc_context_stats",
            "xc_integrate", "xc_strerror", "LIB_PATH", "xc_context_set_timing",
-           "xc_context_set_phi_cache",
+           "xc_context_set_phi_cache", "xc_context_footprint",
            "xc_context_timing", "PHASES", "xc_engine_create", "xc_engine_add_request",
            "xc_engine_submit", "xc_engine_step", "xc_engine_poll", "xc_engine_release",
            "xc_engine_stats", "xc_engine_destroy"]

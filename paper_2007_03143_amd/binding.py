@@ -146,6 +146,8 @@ def _load():
     lib.xc_context_set_timing.argtypes = [c_void_p, c_int]
     lib.xc_context_set_phi_cache.restype = c_int
     lib.xc_context_set_phi_cache.argtypes = [c_void_p, c_int]
+    lib.xc_context_footprint.restype = c_int
+    lib.xc_context_footprint.argtypes = [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]
     lib.xc_context_timing.restype = c_int
     lib.xc_context_timing.argtypes = [c_void_p, POINTER(XcTiming)]
     lib.xc_context_destroy.restype = c_int
@@ -298,6 +300,13 @@ def xc_context_set_phi_cache(handle, enable):
     _check(LIB.xc_context_set_phi_cache(handle, 1 if enable else 0))
 
 
+def xc_context_footprint(handle):
+    """(min_bytes, cached_bytes) of the context's integrations."""
+    mn, al = c_size_t(), c_size_t()
+    _check(LIB.xc_context_footprint(handle, byref(mn), byref(al)))
+    return mn.value, al.value
+
+
 def xc_context_timing(handle):
     t = XcTiming()
     _check(LIB.xc_context_timing(handle, byref(t)))
@@ -394,6 +403,9 @@ class XcContext:
 
     def set_phi_cache(self, enable):
         xc_context_set_phi_cache(self.handle, enable)
+
+    def footprint(self):
+        return xc_context_footprint(self.handle)
 
     def timing(self):
         return xc_context_timing(self.handle)

@@ -266,19 +266,19 @@ static int plan_waves(xc_context* c) {
         const int ngp = (ng + kColPad - 1) / kColPad * kColPad;
         const int nmt = (nb + kTile - 1) / kTile;
         const size_t slab = (size_t)nbp * ngp;
-        const size_t bytes = 8 * (kSlabs * slab + (size_t)nmt * 4 * ngp);
-        if (cur.count > 0 && used + bytes > budget) close_wave();
         WaveBatch w{};
+        w.nbp = nbp;
+        w.ngp = ngp;
+        w.nmt = nmt;
+        const size_t bytes = batch_scratch_bytes(w);
+        if (cur.count > 0 && used + bytes > budget) close_wave();
         w.phi_off = (long long)(used / 8);
         w.part_off = (long long)(used / 8 + kSlabs * slab);
         w.pt_off = b.begin;
         w.shell_off = c->h_shoff[j];
         w.func_off = c->h_fnoff[j];
         w.nb = nb;
-        w.nbp = nbp;
         w.ng = ng;
-        w.ngp = ngp;
-        w.nmt = nmt;
         w.nshell = c->h_nsh[j];
         w.batch = (int)j;
         w.req = 0;
@@ -312,6 +312,16 @@ static int plan_waves(xc_context* c) {
     XC_TRY(dev_reserve(c->npart, 8 * (size_t)std::max<long long>(1, c->n_batches)));
     XC_HIP(hipStreamSynchronize(c->stream));
     return XC_OK;
+}
+
+size_t estimate_build_bytes(const xc_context* c) {
+    // points, weights and build temporaries scale with the nominal grid;
+    // screening lists with points x basis size
+    const double npts = (double)c->n_rad * c->n_ang * (double)c->gatoms.size();
+    const double build = npts * (32.0 + 80.0 + 8.0);
+    const double lists = npts / 64.0 * (8.0 + 8.0 * std::min(c->nbf, 4096));
+    const double fixed = 8.0 * c->natoms * (double)c->natoms + 4096.0 * 1024.0;
+    return (size_t)(build + lists + fixed);
 }
 
 int build_grid(xc_context* c) {
@@ -496,6 +506,50 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
     for (const DevBuf* b : bufs) pers += b->cap;
     s->persistent_bytes = pers;
     s->wave_bytes = c->max_wave_bytes;
+    return XC_OK;
+}
+
+int xc_context_footprint(xc_context* c, size_t* min_bytes, size_t* cached_bytes) {
+    g_last_error.clear();
+    if (!c) return fail(XC_ERR_INVALID_ARG, "null context");
+    size_t mn = 0, all = 0;
+    if (c->built) {
+        // persistent buffers except those that follow the wave plan (tile
+        // map, per-wave tile-count prefixes)
+        const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells,
+                                &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
+                                &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py,
+                                &c->pz, &c->pw, &c->pidx, &c->batches, &c->shell_list,
+                                &c->shell_loff, &c->func_list, &c->d_wb, &c->epart,
+                                &c->npart, &c->d_req};
+        size_t core = 0;
+        for (const DevBuf* b : bufs) core += b->cap;
+        size_t big = 0, sum = 0;
+        long long tiles_big = 1, gt_all = 0, st_all = 0;
+        for (const WaveBatch& w : c->h_wb) {
+            big = std::max(big, batch_scratch_bytes(w));
+            sum += batch_scratch_bytes(w);
+            tiles_big = std::max<long long>(tiles_big, batch_tiles(w));
+            gt_all += (long long)w.nmt * (w.ngp / kTile);
+            st_all += (long long)w.nmt * (w.nmt + 1) / 2;
+        }
+        const size_t nbat = c->h_wb.size();
+        // two prefix arrays of 1 + batches + waves ints each
+        const size_t pre_each = 2 * sizeof(int) * (1 + 2 * nbat);
+        const size_t pre_one = 2 * sizeof(int) * (nbat ? nbat + 2 : 1);
+        mn = core + pre_each + big + 8 * (size_t)tiles_big;
+        all = core + pre_one + sum + 8 * (size_t)std::max<long long>(1, std::max(gt_all, st_all));
+    } else {
+        // before screening n_b is unknown: bound one batch by the whole basis
+        const size_t nbp = (size_t)(c->nbf + kRowPad - 1) / kRowPad * kRowPad;
+        const size_t ngp = (size_t)(c->batch_max + kColPad - 1) / kColPad * kColPad;
+        const size_t nmt = (size_t)(c->nbf + kTile - 1) / kTile;
+        mn = estimate_build_bytes(c) + 8 * (kSlabs * nbp * ngp + nmt * 4 * ngp) +
+             8 * nmt * std::max(ngp / kTile, (nmt + 1) / 2);
+        all = 0;
+    }
+    if (min_bytes) *min_bytes = mn;
+    if (cached_bytes) *cached_bytes = all;
     return XC_OK;
 }
 

@@ -62,21 +62,6 @@ namespace xc {
 
 int build_grid(xc_context* c);
 
-static size_t batch_bytes(const WaveBatch& w) {
-    return 8 * (kSlabs * (size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
-}
-
-// Device bytes an unbuilt context is expected to need while it is built and
-// afterwards (points, weights and temporaries scale with the nominal grid;
-// screening lists with points x basis size).
-static size_t estimate_bytes(const xc_context* c) {
-    const double npts = (double)c->n_rad * c->n_ang * (double)c->gatoms.size();
-    const double build = npts * (32.0 + 80.0 + 8.0);
-    const double lists = npts / 64.0 * (8.0 + 8.0 * std::min(c->nbf, 4096));
-    const double fixed = 8.0 * c->natoms * (double)c->natoms + 4096.0 * 1024.0;
-    return (size_t)(build + lists + fixed);
-}
-
 static int admit(xc_engine* e) {
     for (auto it = e->waiting.begin(); it != e->waiting.end();) {
         Request* r = e->reqs[*it];
@@ -96,7 +81,7 @@ static int admit(xc_engine* e) {
         e->used += r->bytes;
         r->admitted = true;
         for (const WaveBatch& w : r->ctx->h_wb)
-            if (batch_bytes(w) > e->wave_bytes)
+            if (batch_scratch_bytes(w) > e->wave_bytes)
                 return fail(XC_ERR_NOMEM, "a batch is larger than the engine's wave scratch");
         it = e->waiting.erase(it);
     }
@@ -157,7 +142,7 @@ static int engine_step(xc_engine* e, int* launched) {
             xc_context* c = r->ctx;
             if (in->next_batch >= c->n_batches) continue;
             WaveBatch w = c->h_wb[in->next_batch];
-            const size_t bytes = batch_bytes(w);
+            const size_t bytes = batch_scratch_bytes(w);
             if (used + bytes > e->wave_bytes) continue;
             const int key = r->precision * 2 + (r->functional == XC_GGA_PBE ? 1 : 0);
             Group& g = groups[key];
@@ -307,7 +292,7 @@ int xc_engine_add_request(xc_engine* e, const xc_molecule* mol, const xc_basis* 
     r->ctx = c;
     r->functional = functional;
     r->precision = precision;
-    r->est_bytes = estimate_bytes(c);
+    r->est_bytes = estimate_build_bytes(c);
     if (r->est_bytes > e->budget) {
         xc_context_destroy(c);
         delete r;

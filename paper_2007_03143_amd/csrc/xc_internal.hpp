@@ -81,6 +81,18 @@ struct WaveBatch {
     int req;            // index of the request descriptor (ReqDev) of the launch
 };
 
+// Wave-scratch bytes of one batch: Phi and Z slabs plus the density
+// partials (four per row tile and padded point).
+inline size_t batch_scratch_bytes(const WaveBatch& w) {
+    return 8 * (kSlabs * (size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
+}
+
+// Larger of the batch's density-GEMM and potential-SYR2K tile counts.
+inline int batch_tiles(const WaveBatch& w) {
+    const int gt = w.nmt * (w.ngp / kTile), st = w.nmt * (w.nmt + 1) / 2;
+    return gt > st ? gt : st;
+}
+
 // Everything a launch needs about the request (context + one integration)
 // a batch belongs to; a launch may mix batches of many requests.
 struct ReqDev {
@@ -217,6 +229,10 @@ int upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s);
 int build_grid(xc_context* c);
 void release_build_temporaries(xc_context* c);
 size_t device_bytes(const xc_context* c);
+// Device bytes an unbuilt context is expected to need for its build and its
+// persistent data (no wave scratch): an estimate from the nominal grid size
+// and the basis size.
+size_t estimate_build_bytes(const xc_context* c);
 
 // grid.hip
 int launch_shell_setup(xc_context* c);

@@ -357,3 +357,30 @@ def test_one_shot_host_entry_matches_oracle(functional):
                                      functional, w.P, "fp32v")
     assert E32 == E and N32 == N
     assert np.abs(V32 - Vo).max() <= 1e-4
+
+
+def test_footprint_matches_the_built_plan():
+    """xc_context_footprint: before the build an estimate of min_bytes only;
+    after it, cached_bytes is exactly what a one-wave context holds and
+    min_bytes what a context with one batch per wave holds."""
+    from paper_2007_03143_amd import XcContext
+    w = cfg_water_cluster(n_waters=4, n_rad=30, n_ang=110)
+    g = grid_spec_dict(w)
+    one = XcContext(w.coords, w.mk_alpha, w.basis, g)
+    each = XcContext(w.coords, w.mk_alpha, w.basis, g, wave_bytes=1)
+    try:
+        mn0, al0 = one.footprint()
+        assert mn0 > 0 and al0 == 0
+        one.build_grid()
+        each.build_grid()
+        mn, al = one.footprint()
+        st1, st2 = one.stats(), each.stats()
+        say(f"case footprint: estimate {mn0}, min {mn}, cached {al}, batches {st1['n_batches']}")
+        assert st1["n_waves"] == 1 and st2["n_waves"] == st2["n_batches"] > 1
+        assert al == st1["persistent_bytes"] + st1["wave_bytes"]
+        assert each.footprint() == (mn, al)
+        assert mn == st2["persistent_bytes"] + st2["wave_bytes"]
+        assert 0 < mn < al
+    finally:
+        one.close()
+        each.close()

@@ -591,34 +591,33 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 }
 
 // ------------------------------------------------- functional + Z matrix --
-// One workgroup per batch: rho, grad rho from the partials, the functional
-// per point, the batch's E_xc and N_e partials, then Z^j (eq. z_mat) from
-// phi and grad phi re-evaluated from the shell data (each lane a point, the
-// wave's shells in turn), stored in slab 1.
-template <bool GGA, typename T>
-__global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb,
-                                                const ReqDev* __restrict__ reqs,
-                                                char* __restrict__ scratch) {
-    exp_table_init();
+// Functional: one workgroup per batch, one thread per point: rho, grad rho
+// from the partials, the functional, the batch's E_xc and N_e partials, and
+// the point's Z factors a = w v_rho / 2 and b = 2 w v_sigma grad rho, written
+// over the first row tile's partials (each thread reads all of its point's
+// partials before it writes there, and no other thread touches that point).
+template <bool GGA>
+__global__ __launch_bounds__(256) void k_func(const WaveBatch* __restrict__ wb,
+                                              const ReqDev* __restrict__ reqs,
+                                              char* __restrict__ scratch) {
     const WaveBatch B = wb[blockIdx.x];
     const ReqG R = global_view(reqs[B.req]);
     const gptr<const double> W = R.pw;
     const double rho_thresh = R.rho_thresh;
-    __shared__ double sa[kMaxBatch], sbx[kMaxBatch], sby[kMaxBatch], sbz[kMaxBatch];
     __shared__ double red[256];
-    const double* part = (const double*)(scratch + 8 * B.part_off);
+    double* part = (double*)(scratch + 8 * B.part_off);
     double eacc = 0.0, nacc = 0.0;
     for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
         double a = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
         if (i < B.ng) {
             double rho = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
             for (int mt = 0; mt < B.nmt; ++mt) {
-                const double* p = part + (size_t)mt * 4 * B.ngp + i;
-                rho += p[0];
+                const double* pp = part + (size_t)mt * 4 * B.ngp + i;
+                rho += pp[0];
                 if (GGA) {
-                    gx += p[B.ngp];
-                    gy += p[2 * B.ngp];
-                    gz += p[3 * B.ngp];
+                    gx += pp[B.ngp];
+                    gy += pp[2 * B.ngp];
+                    gz += pp[3 * B.ngp];
                 }
             }
             const double w = W[B.pt_off + i];
@@ -645,10 +644,10 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
                 }
             }
         }
-        sa[i] = a;
-        sbx[i] = bx;
-        sby[i] = by;
-        sbz[i] = bz;
+        part[i] = a;
+        part[(size_t)B.ngp + i] = bx;
+        part[2 * (size_t)B.ngp + i] = by;
+        part[3 * (size_t)B.ngp + i] = bz;
     }
     const double es = block_sum_256(eacc, red);
     const double ns = block_sum_256(nacc, red);
@@ -656,13 +655,27 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
         R.epart[B.batch] = es;
         R.npart[B.batch] = ns;
     }
+}
+
+// Z^j (eq. z_mat), stored in slab 1: z = a phi + b . grad phi with phi and
+// grad phi re-evaluated from the shell data. One workgroup per batch; each
+// lane takes a point (its coordinates and Z factors read once), the wave
+// takes shells wave, wave + 4, ... of the batch's list. No LDS and few
+// registers, so many workgroups share a CU.
+template <typename T>
+__global__ __launch_bounds__(256) void k_z(const WaveBatch* __restrict__ wb,
+                                           const ReqDev* __restrict__ reqs,
+                                           char* __restrict__ scratch) {
+    exp_table_init();
+    const WaveBatch B = wb[blockIdx.x];
+    const ReqG R = global_view(reqs[B.req]);
+    const double* fac = (const double*)(scratch + 8 * B.part_off);
     T* Zm = (T*)(scratch + 8 * (B.phi_off + (long long)B.nbp * B.ngp));
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) Zm[(size_t)B.nb * B.ngp + k] = T(0);
+    __syncthreads();  // the exponential table
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    // each lane takes a point (its coordinates and Z factors read once), the
-    // wave takes shells wave, wave + 4, ... of the batch's list
     for (int i = lane; i < B.ngp; i += 64) {
         const bool hasp = i < B.ng;
         double px = 0.0, py = 0.0, pz = 0.0;
@@ -671,7 +684,8 @@ __global__ __launch_bounds__(256) void k_func_z(const WaveBatch* __restrict__ wb
             py = R.py[B.pt_off + i];
             pz = R.pz[B.pt_off + i];
         }
-        const double a = sa[i], bx = sbx[i], by = sby[i], bz = sbz[i];
+        const double a = fac[i], bx = fac[(size_t)B.ngp + i], by = fac[2 * (size_t)B.ngp + i],
+                     bz = fac[3 * (size_t)B.ngp + i];
         for (int sl = wave; sl < B.nshell; sl += 4) {
             const int sidx = R.shell_list[B.shell_off + sl];
             const int loff = R.shell_loff[B.shell_off + sl];
@@ -1301,7 +1315,9 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
     }
     {
         PhaseScope ps(timer, s, XC_PHASE_FUNCTIONAL);
-        hipLaunchKernelGGL((k_func_z<GGA, TZ>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        hipLaunchKernelGGL((k_func<GGA>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        XC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_z<TZ>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (syr_tiles > 0) {
@@ -1338,7 +1354,9 @@ static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b
     }
     {
         PhaseScope ps(timer, s, XC_PHASE_FUNCTIONAL);
-        hipLaunchKernelGGL((k_func_z<GGA, float>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        hipLaunchKernelGGL((k_func<GGA>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        XC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_z<float>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (syr_tiles > 0) {

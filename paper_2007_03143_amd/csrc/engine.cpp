@@ -3,7 +3,7 @@
 // footprint; an admitted request's grid, weights, batches and screening
 // lists stay on the device across its iterations (grid reuse, Sec. 2.3.1);
 // every step co-batches the pending grid batches of all in-flight
-// integrations into the same four launches (Alg. 4 over a mixed batch set).
+// integrations into the same launches (Alg. 4 over a mixed batch set).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -2,7 +2,8 @@
 // eval_local_den_grad, eq. x_mat, eq. exc_batch, eq. vxc_inc, eq. vxc_batch,
 // eq. z_mat; Sec. 2.3.2 Alg. 4).
 //
-// For every batch j of a wave, in four launches over all its batches:
+// For every batch j of a wave, in four steps, each one or two launches over
+// all its batches:
 //  1. collocation Phi^j (n_b x n_g), written in compressed form over the
 //     screened functions (only Phi is stored; gradients are re-evaluated
 //     from the shell data wherever they are needed, which costs far less
@@ -10,8 +11,9 @@
 //  2. X = P^j Phi^j on MFMA with P^j gathered straight from the full P
 //     (never packed), and rho, grad rho reduced from X in the epilogue
 //     (X is never stored);
-//  3. the functional per point, the batch's E_xc and N_e partials, and
-//     Z^j = (1/2) w v_rho Phi + 2 w v_sigma grad rho . grad Phi;
+//  3. the functional per point, the batch's E_xc and N_e partials (one
+//     kernel), then Z^j = (1/2) w v_rho Phi + 2 w v_sigma grad rho . grad Phi
+//     (another);
 //  4. V^j = Z Phi^T + Phi Z^T on MFMA over lower-triangle tiles only,
 //     added into the lower triangle of the full V with FP64 atomics.
 // Then V is mirrored and E_xc, N_e are summed in a fixed order.

@@ -249,7 +249,7 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
                   double* dV, double* dEN);
 // Request descriptor of an integration of context c with the given buffers.
 ReqDev make_req(const xc_context* c, const double* dP, double* dV);
-// The four per-wave launches (collocation, density, functional + Z,
+// The per-wave launches (collocation, density, functional, Z,
 // potential) over count batches whose descriptors are already on the device.
 // d_tmap: room for 2 * max(gemm_tiles, syr_tiles) ints (tile -> batch map).
 // colloc = false skips the collocation kernel: the scratch already holds Phi

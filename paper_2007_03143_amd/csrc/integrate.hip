@@ -711,8 +711,9 @@ __global__ __launch_bounds__(256) void k_z(const WaveBatch* __restrict__ wb,
 // ------------------------------------------------------ potential (SYR2K) --
 // Lower-triangle tile (I >= J) of V^j = Z Phi^T + Phi Z^T, 64 x 64, over all
 // points of the batch, added into V[f(row)][f(col)] (f ascending, so the
-// global entry is in the lower triangle too). T is the arithmetic (and the
-// storage of Z), TP the storage of Phi.
+// global entry is in the lower triangle too). A diagonal tile (I = J) loads
+// its row operands only and reads them again as its column operands. T is
+// the arithmetic (and the storage of Z), TP the storage of Phi.
 template <typename T, typename TP>
 __global__ __launch_bounds__(256) void k_syr2k(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
@@ -762,6 +763,10 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const int wm = wave >> 1, wn = wave & 1;
     const int lr = tid >> 2, lc = (tid & 3) * 2;
     const int rI = I * kTile + lr, rJ = J * kTile + lr;
+    // a diagonal tile's column operands are its row operands
+    const bool diag = I == J;
+    T (*tPJ)[kTile][KP] = diag ? sPI : sPJ;
+    T (*tZJ)[kTile][KP] = diag ? sZI : sZJ;
     const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
     const T* zI = Zm + (size_t)(vI ? rI : 0) * B.ngp;
     const TP* pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
@@ -781,23 +786,38 @@ __global__ __launch_bounds__(256) void k_syr2k(
             for (int q = 0; q < 2; ++q) {
                 g[0][q] = zI[k0 + q];
                 ph[0][q] = pI[k0 + q];
-                ph[1][q] = pJ[k0 + q];
-                g[3][q] = zJ[k0 + q];
+            }
+            if (!diag) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    ph[1][q] = pJ[k0 + q];
+                    g[3][q] = zJ[k0 + q];
+                }
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 g[0][q] = vI ? g[0][q] : T(0);
                 g[1][q] = vI ? T(ph[0][q]) : T(0);
-                g[2][q] = vJ ? T(ph[1][q]) : T(0);
-                g[3][q] = vJ ? g[3][q] : T(0);
+            }
+            if (!diag) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    g[2][q] = vJ ? T(ph[1][q]) : T(0);
+                    g[3][q] = vJ ? g[3][q] : T(0);
+                }
             }
         } else {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 g[0][q] = vI ? zI[k0 + q] : T(0);
                 g[1][q] = vI ? pI[k0 + q] : T(0);
-                g[2][q] = vJ ? pJ[k0 + q] : T(0);
-                g[3][q] = vJ ? zJ[k0 + q] : T(0);
+            }
+            if (!diag) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    g[2][q] = vJ ? pJ[k0 + q] : T(0);
+                    g[3][q] = vJ ? zJ[k0 + q] : T(0);
+                }
             }
         }
     };
@@ -806,8 +826,13 @@ __global__ __launch_bounds__(256) void k_syr2k(
         for (int q = 0; q < 2; ++q) {
             sZI[buf][lr][lc + q] = g[0][q];
             sPI[buf][lr][lc + q] = g[1][q];
-            sPJ[buf][lr][lc + q] = g[2][q];
-            sZJ[buf][lr][lc + q] = g[3][q];
+        }
+        if (!diag) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                sPJ[buf][lr][lc + q] = g[2][q];
+                sZJ[buf][lr][lc + q] = g[3][q];
+            }
         }
     };
     typename M::acc acc[2][2];
@@ -847,8 +872,8 @@ __global__ __launch_bounds__(256) void k_syr2k(
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
                 const int r = wn * 32 + nb * 16 + (lane & 15);
-                bp[nb] = sPJ[cur][r][kc];
-                bz[nb] = sZJ[cur][r][kc];
+                bp[nb] = tPJ[cur][r][kc];
+                bz[nb] = tZJ[cur][r][kc];
             }
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)

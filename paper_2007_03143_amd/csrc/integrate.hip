@@ -1119,8 +1119,9 @@ __global__ __launch_bounds__(256) void k_gemm_rho_bf16(
 }
 
 // Potential contraction V^j = Z Phi^T + Phi Z^T in split BF16 (Phi and Z
-// stored in FP32), lower-triangle tiles as in k_syr2k, one LDS buffer with
-// the next step's loads in registers.
+// stored in FP32), lower-triangle tiles as in k_syr2k (diagonal tiles reuse
+// their row operands), one LDS buffer with the next step's loads in
+// registers.
 __global__ __launch_bounds__(256) void k_syr2k_bf16(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
     const ReqDev* __restrict__ reqs, const char* __restrict__ scratch) {
@@ -1165,11 +1166,14 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     const float* src[4] = {Zm + (size_t)(vI ? rI : 0) * B.ngp, Phi + (size_t)(vI ? rI : 0) * B.ngp,
                            Phi + (size_t)(vJ ? rJ : 0) * B.ngp, Zm + (size_t)(vJ ? rJ : 0) * B.ngp};
     const bool valid[4] = {vI, vI, vJ, vJ};
+    // a diagonal tile's column operands are its row operands
+    const bool diag = I == J;
     float4 g[4][2];
     auto gload = [&](int ks) {
         const int k0 = ks * kKB + lk;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
+            if (a >= 2 && diag) continue;
             g[a][0] = *reinterpret_cast<const float4*>(src[a] + k0);
             g[a][1] = *reinterpret_cast<const float4*>(src[a] + k0 + 4);
         }
@@ -1177,6 +1181,7 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     auto sstore = [&]() {
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
+            if (a >= 2 && diag) continue;
             const float x[8] = {g[a][0].x, g[a][0].y, g[a][0].z, g[a][0].w,
                                 g[a][1].x, g[a][1].y, g[a][1].z, g[a][1].w};
             bf16x8 h, l;
@@ -1224,10 +1229,10 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
             const int r = wn * 32 + nb * 16 + (lane & 15);
-            pjh[nb] = *reinterpret_cast<const bf16x8*>(&tile(4)[r][fk]);
-            pjl[nb] = *reinterpret_cast<const bf16x8*>(&tile(5)[r][fk]);
-            zjh[nb] = *reinterpret_cast<const bf16x8*>(&tile(6)[r][fk]);
-            zjl[nb] = *reinterpret_cast<const bf16x8*>(&tile(7)[r][fk]);
+            pjh[nb] = *reinterpret_cast<const bf16x8*>(&tile(diag ? 2 : 4)[r][fk]);
+            pjl[nb] = *reinterpret_cast<const bf16x8*>(&tile(diag ? 3 : 5)[r][fk]);
+            zjh[nb] = *reinterpret_cast<const bf16x8*>(&tile(diag ? 0 : 6)[r][fk]);
+            zjl[nb] = *reinterpret_cast<const bf16x8*>(&tile(diag ? 1 : 7)[r][fk]);
         }
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)

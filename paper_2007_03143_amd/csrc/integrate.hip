@@ -108,13 +108,15 @@ __device__ inline ShellDev load_shell(gptr<const ShellDev> p) {
 // each workgroup fills with the library exp2 (exp_table_init, before its
 // first barrier). About half the FP64 operations of the library exp; within
 // 2 ulp where the result is a normal number (an exact replay of these steps
-// over 5,000 arguments finds at most 1.74 ulp); x beyond the FP64 range gives
-// 0 through ldexp.
+// over 5,000 arguments finds at most 1.74 ulp). The argument is first clamped
+// to 746, where e^{-x} already rounds to zero, so the integer conversion below
+// stays in range for any input (a huge alpha r^2, +inf or NaN all give 0).
 __shared__ double g_exp_tab[64];
 __device__ inline void exp_table_init() {
     if (threadIdx.x < 64) g_exp_tab[threadIdx.x] = exp2(-(double)threadIdx.x / 64.0);
 }
 __device__ inline double exp_neg(double x) {
+    x = fmin(x, 746.0);
     const double nd = rint(x * 92.33248261689366);       // 64 / ln 2
     const int n = (int)nd;
     double r = fma(-nd, 0.010830424696249145, x);         // ln2 (nearest double) / 64

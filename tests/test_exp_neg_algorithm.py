@@ -24,6 +24,13 @@ def _source_constants():
     return c0, c1, c2
 
 
+def _source_clamp():
+    src = open(os.path.join(ROOT, "paper_2007_03143_amd", "csrc", "integrate.hip")).read()
+    body = src[src.index("__device__ inline double exp_neg(double x)"):]
+    body = body[:body.index("\n}\n")]
+    return float(re.search(r"x = fmin\(x, ([0-9.e+-]+)\);", body).group(1))
+
+
 def _rd(q):
     """Nearest double of a rational (round half to even)."""
     return float(q)
@@ -37,7 +44,9 @@ def _table():
     return [_rd(Fraction(Decimal(2) ** (Decimal(-j) / 64))) for j in range(64)]
 
 
-def _exp_neg(x, c0, c1, c2, tab):
+def _exp_neg(x, c0, c1, c2, tab, clamp=None):
+    if clamp is not None:
+        x = clamp if (np.isnan(x) or x > clamp) else x     # fmin(x, clamp)
     nd = float(np.rint(_rd(Fraction(x) * Fraction(c0))))
     n = int(nd)
     r = _fma(-nd, c1, x)
@@ -76,6 +85,17 @@ def test_exp_neg_within_two_ulp():
 
 def test_exp_neg_underflows_to_zero():
     c0, c1, c2 = _source_constants()
+    clamp = _source_clamp()
     tab = _table()
-    assert _exp_neg(750.0, c0, c1, c2, tab) == 0.0
-    assert _exp_neg(0.0, c0, c1, c2, tab) == 1.0
+    # the clamp itself lies where e^{-x} rounds to zero in FP64
+    assert (-Decimal(clamp)).exp() < Decimal(2) ** -1075
+    assert _exp_neg(clamp, c0, c1, c2, tab) == 0.0
+    assert _exp_neg(750.0, c0, c1, c2, tab, clamp) == 0.0
+    assert _exp_neg(0.0, c0, c1, c2, tab, clamp) == 1.0
+    # arguments whose integer conversion would overflow without the clamp
+    # (a tight exponent far outside its cutoff sphere, +inf, NaN)
+    for x in (3e7, 1e300, float("inf"), float("nan")):
+        assert _exp_neg(x, c0, c1, c2, tab, clamp) == 0.0
+    # below the clamp the clamped and plain replays agree
+    for x in (1e-3, 3.0, 700.0, 745.0):
+        assert _exp_neg(x, c0, c1, c2, tab, clamp) == _exp_neg(x, c0, c1, c2, tab)

@@ -39,6 +39,16 @@ def test_water_parity(functional):
     _check(cfg_water(), functional)
 
 
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_f_shell_parity(functional):
+    """Angular momentum 3: an f shell on O and a d shell on each H (47
+    Cartesian functions); the f shell's ten rows straddle the 16-row groups
+    of the density epilogue."""
+    w = cfg_water(polarisation=True)
+    assert 3 in set(w.basis.shell_L.tolist())
+    _check(w, functional)
+
+
 def test_water_no_truncation_parity():
     _check(cfg_water(n_rad=40, n_ang=146), "pbe", screen_eta=0.0)
 

@@ -26,8 +26,9 @@ def test_rcut_definition():
     assert np.isinf(oracle.shell_rcut(alpha, 0.0))
 
 
-def test_collocation_gradient_matches_finite_difference():
-    w = cfg_water()
+@pytest.mark.parametrize("polarisation", [False, True])
+def test_collocation_gradient_matches_finite_difference(polarisation):
+    w = cfg_water(polarisation=polarisation)
     rng = np.random.default_rng(2)
     pts = rng.normal(scale=1.5, size=(40, 3))
     phi, dphi = oracle.collocation(pts, w.coords, w.basis, 0.0)
@@ -58,11 +59,13 @@ def test_collocation_truncation():
         assert np.all(trunc[~inside, blk] == 0.0)
 
 
-def test_grid_overlap_matches_analytic():
+@pytest.mark.parametrize("polarisation", [False, True])
+def test_grid_overlap_matches_analytic(polarisation):
     """sum_i w_i phi_mu phi_nu on the SSF grid reproduces the analytic
     overlap S (independent Gaussian-product formula), so every power,
-    exponent and coefficient of the collocation is pinned."""
-    w = cfg_water(n_rad=100, n_ang=590)
+    exponent and coefficient of the collocation is pinned; with
+    polarisation the basis holds f (L = 3) and d shells."""
+    w = cfg_water(n_rad=100, n_ang=590, polarisation=polarisation)
     pts, wts, _ = oracle.grid_and_weights(
         w.coords, w.mk_alpha, 100, w.ang)
     phi, _ = oracle.collocation(pts, w.coords, w.basis, 0.0, grad=False)

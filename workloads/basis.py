@@ -109,9 +109,11 @@ def _contract(alpha, rng, L):
     return d / np.sqrt(_self_overlap_xL(alpha, d, L))
 
 
-def element_shells(Z, seed, diffuse=None):
+def element_shells(Z, seed, diffuse=None, polarisation=False):
     """The shells (L, alpha, d) of one element; identical for every atom of
-    that element for a given seed."""
+    that element for a given seed. polarisation=True appends one more shell
+    of higher angular momentum (f on C, N, O; d on H), two rungs wide, after
+    the others (the earlier shells are unchanged)."""
     rng = np.random.default_rng([seed, int(Z)])
     out = []
     for L, anchor, where in RECIPES[int(Z)]:
@@ -129,17 +131,21 @@ def element_shells(Z, seed, diffuse=None):
     if diffuse is not None:
         alpha = np.array([float(diffuse)])
         out.append((0, alpha, _contract(alpha, rng, 0)))
+    if polarisation:
+        L = 2 if int(Z) == 1 else 3
+        alpha = LADDER[[3, 2]].copy()
+        out.append((L, alpha, _contract(alpha, rng, L)))
     return out
 
 
-def make_basis(Z, seed=2007, diffuse=None):
+def make_basis(Z, seed=2007, diffuse=None, polarisation=False):
     """Basis for a molecule with atomic numbers Z (shells in atom order)."""
     atom, Ls, npr, al, co = [], [], [], [], []
     cache = {}
     for a, z in enumerate(Z):
         z = int(z)
         if z not in cache:
-            cache[z] = element_shells(z, seed, diffuse)
+            cache[z] = element_shells(z, seed, diffuse, polarisation)
         for L, alpha, d in cache[z]:
             atom.append(a)
             Ls.append(L)

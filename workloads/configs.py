@@ -70,18 +70,20 @@ def grid_spec_dict(w, atom_mask=None, **over):
 
 
 def _finish(name, mol, n_occ, n_rad, n_ang, functional, seed, diffuse=None,
-            with_S=True):
-    basis = make_basis(mol.Z, seed=2007, diffuse=diffuse)
+            with_S=True, polarisation=False):
+    basis = make_basis(mol.Z, seed=2007, diffuse=diffuse, polarisation=polarisation)
     S = overlap_matrix(basis, mol.coords)
     P = random_density(S, n_occ, seed=seed)
     return Workload(name, mol, basis, P, n_occ, n_rad, n_ang, functional,
                     S=S if with_S else None)
 
 
-def cfg_water(functional="lda", n_rad=75, n_ang=302, seed=1):
+def cfg_water(functional="lda", n_rad=75, n_ang=302, seed=1, polarisation=False):
     """One water, ~25 functions, 5 occupied orbitals (tr PS = 10),
-    75 x 302 grid per atom (67,950 points)."""
-    return _finish("water", water(), 5, n_rad, n_ang, functional, seed)
+    75 x 302 grid per atom (67,950 points). polarisation=True adds an f
+    shell on O and a d shell on each H (47 functions)."""
+    return _finish("water_fd" if polarisation else "water", water(), 5, n_rad, n_ang,
+                   functional, seed, polarisation=polarisation)
 
 
 def cfg_water_cluster(n_waters=64, functional="pbe", n_rad=100, n_ang=590,

@@ -232,6 +232,34 @@ int xc_context_integrate(xc_context* ctx, int functional, int precision,
                          const double* d_P, double* d_V, double* d_EN);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * integration as xc_context_integrate (same kernels, same arguments and
+ * results), with its per-integration scratch (the Phi and Z slabs and density
+ * partials of a wave, the tile map, the request descriptor) placed in a
+ * static device array of XC_STATIC_SCRATCH_BYTES instead of the context's
+ * own scratch. It calls no hipMalloc, hipFree or other allocating routine.
+ *  - The context must be built (xc_context_build_grid) and its device must be
+ *    the current device: XC_ERR_STATE otherwise.
+ *  - The context's largest wave, plus 256 bytes and its tile map, must fit
+ *    in the array: XC_ERR_NOMEM otherwise (nothing is launched, no output is
+ *    written). A context created with wave_bytes <= XC_STATIC_SCRATCH_BYTES / 2
+ *    fits whenever one batch does (a 512-point batch with n_b screened
+ *    functions needs about 8.2 n_b KiB).
+ *  - The library holds one such array on every GPU it runs on, until the
+ *    process ends; the first call on a device looks up its address. Every
+ *    call on one GPU shares that GPU's array, which keeps the last call's
+ *    contents; nothing in it has to start at zero (each call writes every
+ *    byte it later reads). Calls that overlap on one GPU (from other streams,
+ *    contexts or threads) race on the array: the caller must order them.
+ *  - The context's Phi cache (xc_context_set_phi_cache) is neither used nor
+ *    disturbed, and per-phase timing is not recorded.
+ */
+#define XC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int xc_context_integrate_noalloc(xc_context* ctx, int functional, int precision,
+                                 const double* d_P, double* d_V, double* d_EN);
+
+/*
  * Device memory of this context's integrations, for admission decisions
  * (the batch-subset waves of Alg. 2 are planned against a memory budget).
  *  min_bytes     persistent data (grid, batches, screened lists,

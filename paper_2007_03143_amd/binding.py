@@ -133,6 +133,9 @@ def _load():
     lib.xc_context_integrate.restype = c_int
     lib.xc_context_integrate.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p,
                                          c_void_p]
+    lib.xc_context_integrate_noalloc.restype = c_int
+    lib.xc_context_integrate_noalloc.argtypes = [c_void_p, c_int, c_int, c_void_p,
+                                                 c_void_p, c_void_p]
     lib.xc_context_stats.restype = c_int
     lib.xc_context_stats.argtypes = [c_void_p, POINTER(XcStats)]
     lib.xc_context_export_grid.restype = c_int
@@ -261,6 +264,17 @@ def xc_context_integrate(handle, functional, precision, d_P, d_V, d_EN):
     _check(LIB.xc_context_integrate(handle, _code(FUNCTIONALS, functional),
                                     _code(PRECISIONS, precision), c_void_p(d_P),
                                     c_void_p(d_V), c_void_p(d_EN)))
+
+
+def xc_context_integrate_noalloc(handle, functional, precision, d_P, d_V, d_EN):
+    """xc_context_integrate with the scratch in the library's static device
+    array (no allocation); device pointers (ints)."""
+    _check(LIB.xc_context_integrate_noalloc(handle, _code(FUNCTIONALS, functional),
+                                            _code(PRECISIONS, precision), c_void_p(d_P),
+                                            c_void_p(d_V), c_void_p(d_EN)))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def xc_context_stats(handle):

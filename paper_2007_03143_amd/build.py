@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libxc_mi355x.so")
-SOURCES = ["abi.cpp", "engine.cpp", "grid.hip", "batching.hip", "integrate.hip"]
+SOURCES = ["abi.cpp", "engine.cpp", "grid.hip", "batching.hip", "integrate.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 

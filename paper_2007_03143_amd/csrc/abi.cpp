@@ -305,7 +305,9 @@ static int plan_waves(xc_context* c) {
     XC_TRY(upload(c->d_syr_pre, spre.data(), sizeof(int) * spre.size(), c->stream));
     int max_tiles = 1;
     for (const Wave& w : c->waves) max_tiles = std::max({max_tiles, w.gemm_tiles, w.syr_tiles});
+    c->max_tiles = max_tiles;
     XC_TRY(dev_reserve(c->d_tmap, 2 * sizeof(int) * (size_t)max_tiles));
+    XC_TRY(dev_reserve(c->d_req, sizeof(ReqDev)));
     if (!c->external_scratch)
         XC_TRY(dev_reserve(c->scratch, std::max<size_t>(c->max_wave_bytes, 8)));
     XC_TRY(dev_reserve(c->epart, 8 * (size_t)std::max<long long>(1, c->n_batches)));
@@ -479,6 +481,16 @@ int xc_context_integrate(xc_context* c, int functional, int precision, const dou
     return run_integrate(c, functional, precision, dP, dV, dEN);
 }
 
+int xc_context_integrate_noalloc(xc_context* c, int functional, int precision,
+                                 const double* dP, double* dV, double* dEN) {
+    g_last_error.clear();
+    if (!c) return fail(XC_ERR_INVALID_ARG, "null context");
+    if (!dP || !dV || !dEN) return fail(XC_ERR_INVALID_ARG, "null device buffer");
+    XC_TRY(check_func_prec(functional, precision));
+    if (!c->built) return fail(XC_ERR_STATE, "grid not built (building allocates device memory)");
+    return run_integrate_noalloc(c, functional, precision, dP, dV, dEN);
+}
+
 int xc_context_stats(xc_context* c, xc_stats* s) {
     g_last_error.clear();
     if (!c || !s) return fail(XC_ERR_INVALID_ARG, "null context or stats");
@@ -502,7 +514,7 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
                             &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->epart,
-                            &c->npart};
+                            &c->npart, &c->d_req};
     for (const DevBuf* b : bufs) pers += b->cap;
     s->persistent_bytes = pers;
     s->wave_bytes = c->max_wave_bytes;

@@ -1280,6 +1280,8 @@ __global__ void k_tile_map(const int* __restrict__ prefix, int nwb, int2* __rest
     for (int t = t0; t < t1; ++t) map[t] = make_int2(b, t - t0);
 }
 
+__global__ void k_put_req(ReqDev* dst, ReqDev v) { *dst = v; }
+
 __global__ void k_fill(double* p, long long n, double v) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -1445,6 +1447,12 @@ int launch_finish(PhaseTimer* timer, hipStream_t s, double* dV, int nbf,
     return XC_OK;
 }
 
+int launch_put_req(hipStream_t s, ReqDev* dst, const ReqDev& v) {
+    hipLaunchKernelGGL(k_put_req, dim3(1), dim3(1), 0, s, dst, v);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
 int launch_fill(hipStream_t s, double* p, long long n, double v) {
     if (n <= 0) return XC_OK;
     hipLaunchKernelGGL(k_fill, dim3(grid_1d(n, 256)), dim3(256), 0, s, p, n, v);
@@ -1483,8 +1491,8 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
         hipLaunchKernelGGL(k_fill, dim3(grid_1d(nn, 256)), dim3(256), 0, c->stream, dV, nn, 0.0);
         XC_HIP(hipGetLastError());
     }
-    const ReqDev req = make_req(c, dP, dV);
-    XC_TRY(upload(c->d_req, &req, sizeof(ReqDev), c->stream));
+    XC_TRY(dev_reserve(c->d_req, sizeof(ReqDev)));
+    XC_TRY(launch_put_req(c->stream, (ReqDev*)c->d_req.p, make_req(c, dP, dV)));
     const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
     const int* gpre = (const int*)c->d_gemm_pre.p;
     const int* spre = (const int*)c->d_syr_pre.p;

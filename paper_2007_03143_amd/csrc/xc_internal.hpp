@@ -190,6 +190,7 @@ struct xc_context {
     xc::DevBuf d_tmap;           // tile -> (batch, tile in batch) of one launch
     xc::DevBuf scratch;
     size_t max_wave_bytes = 0;
+    int max_tiles = 1;           // most tiles of one contraction launch in any wave
     xc::DevBuf epart, npart;
     xc::DevBuf d_req;            // one ReqDev for the context's own integrations
     bool external_scratch = false;  // wave scratch supplied by an engine
@@ -249,6 +250,9 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
                   double* dV, double* dEN);
 // Request descriptor of an integration of context c with the given buffers.
 ReqDev make_req(const xc_context* c, const double* dP, double* dV);
+// Write one request descriptor to device memory with a one-thread kernel (the
+// descriptor travels as a kernel argument: no host staging buffer).
+int launch_put_req(hipStream_t s, ReqDev* dst, const ReqDev& v);
 // The per-wave launches (collocation, density, functional, Z,
 // potential) over count batches whose descriptors are already on the device.
 // d_tmap: room for 2 * max(gemm_tiles, syr_tiles) ints (tile -> batch map).
@@ -258,6 +262,10 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre,
                 int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
                 char* scratch, int* d_tmap, bool colloc = true);
+// noalloc.hip: the integration with its wave scratch, tile map and request
+// descriptor in the library's static device array (no allocation).
+int run_integrate_noalloc(xc_context* c, int functional, int precision, const double* dP,
+                          double* dV, double* dEN);
 // Bytes per element of the stored Phi under a precision code.
 int phi_elem_bytes(int precision);
 // Fill n doubles with v (a kernel, so it can be captured in a graph).

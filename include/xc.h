@@ -59,10 +59,21 @@ extern "C" {
                                 contractions on FP32 MFMA with FP32 accumulation;
                                 FP64 functional, Z formation, E_xc/N_e sums and V
                                 accumulation */
-#define XC_MIXED_BF16X3  2   /* Phi and Z stored in FP32; both contractions in split
-                                BF16 (x = hi + lo, products hi hi + hi lo + lo hi on
-                                BF16 MFMA, FP32 accumulate); FP64 functional, Z
-                                formation, E_xc/N_e sums and V accumulation */
+#define XC_MIXED_BF16    2   /* split BF16 on BF16 MFMA (v_mfma_f32_16x16x32_bf16) with
+                                FP32 accumulation in both contractions. Density
+                                contraction X = P^j Phi^j (eq. x_mat): every row of P
+                                and every point's column of Phi is scaled by a power
+                                of two and cut into four signed 8-bit digits (the
+                                first 7 bits), so digit products are exact and their
+                                FP32 sums stay exact up to 128 terms, after which
+                                they are added into FP64: X carries about 31 bits
+                                relative to the largest entry of its row of P and
+                                point's column of Phi (10 digit products per FP64
+                                product). Potential contraction: Phi (FP64) and Z
+                                (FP32) split as hi + lo BF16, products
+                                hi hi + hi lo + lo hi (about 16 bits). Collocation
+                                and Phi in FP64; FP64 functional, Z formation,
+                                E_xc/N_e sums and V accumulation */
 #define XC_MIXED_FP32_V  3   /* FP64 collocation and density contraction, so E_xc, N_e
                                 and the functional inputs are as in XC_FP64; Z and the
                                 V^j contraction in FP32 (FP32 MFMA, FP32 accumulate),
@@ -241,8 +252,9 @@ int xc_context_integrate(xc_context* ctx, int functional, int precision,
  * own scratch. It calls no hipMalloc, hipFree or other allocating routine.
  *  - The context must be built (xc_context_build_grid) and its device must be
  *    the current device: XC_ERR_STATE otherwise.
- *  - The context's largest wave, plus 256 bytes and its tile map, must fit
- *    in the array: XC_ERR_NOMEM otherwise (nothing is launched, no output is
+ *  - The context's largest wave, plus 256 bytes, its tile map and (for
+ *    XC_MIXED_BF16) 8 nbf (nbf + 1) bytes of digits of P, must fit in the
+ *    array: XC_ERR_NOMEM otherwise (nothing is launched, no output is
  *    written). A context created with wave_bytes <= XC_STATIC_SCRATCH_BYTES / 2
  *    fits whenever one batch does (a 512-point batch with n_b screened
  *    functions needs about 8.2 n_b KiB).
@@ -303,7 +315,8 @@ int xc_context_export_batches(xc_context* ctx, long long* point_ptr,
  * the grid and the basis only, not on P. When the wave plan has a single
  * wave, the wave scratch still holds Phi after an integration, and the next
  * integration that stores Phi in the same type (FP64 for XC_FP64 and
- * XC_MIXED_FP32_V, FP32 for XC_MIXED_FP32 and XC_MIXED_BF16X3) skips the
+ * XC_MIXED_FP32_V, FP32 for XC_MIXED_FP32, FP64 with per-point digit scales
+ * for XC_MIXED_BF16) skips the
  * collocation kernel; the results are bitwise the same. Costs no device
  * memory. A grid rebuild, a change of the Phi type or enable = 0 drops the
  * cached matrices; a plan with several waves never caches. Default off.

@@ -27,11 +27,11 @@ XC_LDA_SVWN5 = 1
 XC_GGA_PBE = 2
 XC_FP64 = 0
 XC_MIXED_FP32 = 1
-XC_MIXED_BF16X3 = 2
+XC_MIXED_BF16 = 2
 XC_MIXED_FP32_V = 3
 
 FUNCTIONALS = {"lda": XC_LDA_SVWN5, "svwn5": XC_LDA_SVWN5, "pbe": XC_GGA_PBE}
-PRECISIONS = {"fp64": XC_FP64, "fp32": XC_MIXED_FP32, "bf16x3": XC_MIXED_BF16X3,
+PRECISIONS = {"fp64": XC_FP64, "fp32": XC_MIXED_FP32, "bf16": XC_MIXED_BF16,
               "fp32v": XC_MIXED_FP32_V}
 
 

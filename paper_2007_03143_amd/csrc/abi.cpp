@@ -124,7 +124,7 @@ size_t device_bytes(const xc_context* c) {
                             &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch,
-                            &c->epart, &c->npart, &c->d_req};
+                            &c->epart, &c->npart, &c->d_req, &c->pdig, &c->pscale};
     size_t n = 0;
     for (const DevBuf* b : bufs) n += b->cap;
     return n;
@@ -203,7 +203,7 @@ static int check_func_prec(int functional, int precision) {
     if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE)
         return fail(XC_ERR_UNSUPPORTED, "unknown functional");
     if (precision != XC_FP64 && precision != XC_MIXED_FP32 && precision != XC_MIXED_FP32_V &&
-        precision != XC_MIXED_BF16X3)
+        precision != XC_MIXED_BF16)
         return fail(XC_ERR_UNSUPPORTED, "precision not available");
     return XC_OK;
 }
@@ -219,7 +219,7 @@ static void release_all(xc_context* c) {
                       &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                       &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                       &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch, &c->epart,
-                      &c->npart, &c->d_req};
+                      &c->npart, &c->d_req, &c->pdig, &c->pscale};
     for (DevBuf* b : bufs) dev_release(*b);
 }
 
@@ -227,7 +227,7 @@ static void release_all(xc_context* c) {
 // gradient, or Z, plus density partials) fits the budget (Alg. 2: subsets
 // that saturate device memory), and build each wave's tile tables.
 static int plan_waves(xc_context* c) {
-    c->phi_cached_bytes = 0;
+    c->phi_cached_kind = 0;
     c->waves.clear();
     c->h_wb.clear();
     std::vector<int> gpre, spre;
@@ -328,7 +328,7 @@ size_t estimate_build_bytes(const xc_context* c) {
 
 int build_grid(xc_context* c) {
     c->built = false;
-    c->phi_cached_bytes = 0;
+    c->phi_cached_kind = 0;
     const long long npa = (long long)c->n_rad * c->n_ang;
     c->n_nominal = npa * (long long)c->gatoms.size();
     if (c->n_nominal == 0) {
@@ -629,7 +629,7 @@ int xc_context_set_phi_cache(xc_context* c, int enable) {
     g_last_error.clear();
     if (!c) return fail(XC_ERR_INVALID_ARG, "null context");
     c->phi_cache = enable != 0;
-    if (!c->phi_cache) c->phi_cached_bytes = 0;
+    if (!c->phi_cache) c->phi_cached_kind = 0;
     return XC_OK;
 }
 

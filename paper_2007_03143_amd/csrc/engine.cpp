@@ -11,6 +11,7 @@
 #include <deque>
 #include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "xc_internal.hpp"
@@ -27,6 +28,7 @@ struct Integration {
     bool started = false;
     bool launched_finish = false;
     hipEvent_t done = nullptr;
+    int error = XC_OK;          // its request could not be admitted
 };
 
 struct Request {
@@ -38,6 +40,8 @@ struct Request {
     size_t bytes = 0;
     bool admitted = false;
     bool released = false;
+    int error = XC_OK;          // set when the request cannot be admitted
+    std::string error_msg;
     std::deque<Integration*> queued;
     Integration* active = nullptr;
 };
@@ -73,16 +77,36 @@ static int admit(xc_engine* e) {
             ++it;
             continue;
         }
-        r->ctx->external_scratch = true;
-        int rc = build_grid(r->ctx);
-        if (rc != XC_OK) return rc;
-        release_build_temporaries(r->ctx);
-        r->bytes = device_bytes(r->ctx);
+        xc_context* c = r->ctx;
+        c->external_scratch = true;
+        int rc = build_grid(c);
+        if (rc == XC_OK) {
+            release_build_temporaries(c);
+            for (const WaveBatch& w : c->h_wb)
+                if (batch_scratch_bytes(w) > e->wave_bytes) {
+                    rc = fail(XC_ERR_NOMEM, "a batch is larger than the engine's wave scratch");
+                    break;
+                }
+        }
+        if (rc == XC_OK && r->precision == XC_MIXED_BF16) {
+            rc = dev_reserve(c->pdig, 8 * (size_t)c->nbf * c->nbf);
+            if (rc == XC_OK) rc = dev_reserve(c->pscale, 8 * (size_t)c->nbf);
+        }
+        if (rc != XC_OK) {
+            // the request can never run: it leaves the queue with its device
+            // memory released, and its integrations report the error
+            r->error = rc;
+            r->error_msg = xc_last_error();
+            for (Integration* in : r->queued) in->error = rc;
+            r->queued.clear();
+            xc_context_destroy(c);
+            r->ctx = nullptr;
+            it = e->waiting.erase(it);
+            return rc;
+        }
+        r->bytes = device_bytes(c);
         e->used += r->bytes;
         r->admitted = true;
-        for (const WaveBatch& w : r->ctx->h_wb)
-            if (batch_scratch_bytes(w) > e->wave_bytes)
-                return fail(XC_ERR_NOMEM, "a batch is larger than the engine's wave scratch");
         it = e->waiting.erase(it);
     }
     return XC_OK;
@@ -122,12 +146,17 @@ static int engine_step(xc_engine* e, int* launched) {
     std::sort(act.begin(), act.end(),
               [](const Integration* a, const Integration* b) { return a->ticket < b->ticket; });
     if (act.empty()) return XC_OK;
-    // zero V of integrations that start now
+    // zero V (and cut P into digits in split-BF16 mode) of integrations that
+    // start now
     for (Integration* in : act) {
         if (in->started) continue;
-        const int nbf = e->reqs[in->req]->ctx->nbf;
+        const Request* r = e->reqs[in->req];
+        const int nbf = r->ctx->nbf;
         const long long nn = (long long)nbf * nbf;
         XC_TRY(launch_fill(e->stream, in->V, nn, 0.0));
+        if (r->precision == XC_MIXED_BF16)
+            XC_TRY(launch_p_digits(e->stream, in->P, nbf, (unsigned long long*)r->ctx->pdig.p,
+                                   (double*)r->ctx->pscale.p));
         in->started = true;
     }
     // round-robin: one batch of each in-flight integration at a time until the
@@ -278,7 +307,7 @@ int xc_engine_add_request(xc_engine* e, const xc_molecule* mol, const xc_basis* 
     if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE)
         return fail(XC_ERR_UNSUPPORTED, "unknown functional");
     if (precision != XC_FP64 && precision != XC_MIXED_FP32 && precision != XC_MIXED_FP32_V &&
-        precision != XC_MIXED_BF16X3)
+        precision != XC_MIXED_BF16)
         return fail(XC_ERR_UNSUPPORTED, "precision not available");
     xc_device_opts o{e->stream, 0};
     xc_context* c = nullptr;
@@ -293,6 +322,7 @@ int xc_engine_add_request(xc_engine* e, const xc_molecule* mol, const xc_basis* 
     r->functional = functional;
     r->precision = precision;
     r->est_bytes = estimate_build_bytes(c);
+    if (precision == XC_MIXED_BF16) r->est_bytes += 8 * (size_t)c->nbf * (c->nbf + 1);
     if (r->est_bytes > e->budget) {
         xc_context_destroy(c);
         delete r;
@@ -311,6 +341,8 @@ int xc_engine_submit(xc_engine* e, long long req_id, const double* d_P, double* 
     auto it = e->reqs.find(req_id);
     if (it == e->reqs.end() || it->second->released)
         return fail(XC_ERR_INVALID_ARG, "unknown or released request");
+    if (it->second->error != XC_OK)
+        return fail(it->second->error, "request could not be admitted: " + it->second->error_msg);
     Integration* in = new (std::nothrow) Integration();
     if (!in) return fail(XC_ERR_NOMEM, "host allocation failed");
     in->ticket = e->next_ticket++;
@@ -336,6 +368,12 @@ int xc_engine_poll(xc_engine* e, long long ticket, int* done) {
     if (it == e->tickets.end()) return fail(XC_ERR_INVALID_ARG, "unknown ticket");
     Integration* in = it->second;
     *done = 0;
+    if (in->error != XC_OK) {
+        const int rc = in->error;
+        e->tickets.erase(it);
+        delete in;
+        return fail(rc, "the ticket's request could not be admitted");
+    }
     if (!in->done) return XC_OK;
     hipError_t q = hipEventQuery(in->done);
     if (q == hipErrorNotReady) return XC_OK;

@@ -59,6 +59,8 @@ struct ReqG {
     gptr<const int> shell_list, shell_loff, func_list, func_shell;
     gptr<const double> px, py, pz, pw, P;
     gptr<double> V, epart, npart;
+    gptr<const unsigned long long> Pdig;
+    gptr<const double> Pscale;
     double rho_thresh;
     int nbf;
 };
@@ -80,6 +82,8 @@ __device__ inline ReqG global_view(const ReqDev& r) {
     g.V = to_global(r.V);
     g.epart = to_global(r.epart);
     g.npart = to_global(r.npart);
+    g.Pdig = to_global(r.Pdig);
+    g.Pscale = to_global(r.Pscale);
     g.rho_thresh = r.rho_thresh;
     g.nbf = r.nbf;
     return g;
@@ -199,9 +203,11 @@ __device__ inline void z_shell(double dx, double dy, double dz, double rad, doub
     }
 }
 
+// phi of the (L+1)(L+2)/2 components of one shell at one point, written
+// down the rows starting at out; returns the largest magnitude (FP64).
 template <int L, typename T>
-__device__ inline void phi_shell(double dx, double dy, double dz, double rad, T* out,
-                                 int ngp) {
+__device__ inline double phi_shell(double dx, double dy, double dz, double rad, T* out,
+                                   int ngp) {
     double xp[L + 1], yp[L + 1], zp[L + 1];
     xp[0] = yp[0] = zp[0] = 1.0;
 #pragma unroll
@@ -210,22 +216,30 @@ __device__ inline void phi_shell(double dx, double dy, double dz, double rad, T*
         yp[k] = yp[k - 1] * dy;
         zp[k] = zp[k - 1] * dz;
     }
+    double mx = 0.0;
     int c = 0;
 #pragma unroll
     for (int l = L; l >= 0; --l) {
 #pragma unroll
         for (int m = L - l; m >= 0; --m) {
-            out[(size_t)c * ngp] = T(xp[l] * yp[m] * zp[L - l - m] * rad);
+            const double v = xp[l] * yp[m] * zp[L - l - m] * rad;
+            mx = fmax(mx, fabs(v));
+            out[(size_t)c * ngp] = T(v);
             ++c;
         }
     }
+    return mx;
 }
 
 // One workgroup per batch; wave w evaluates shells w, w+4, ... of the
 // batch's screened list, one lane per point, so a wave never diverges on
 // the contraction length. Points of the batch are staged in LDS. Values are
-// formed in FP64 in every mode and rounded once on store.
-template <typename T>
+// formed in FP64 in every mode and rounded once on store. SCALE (split-BF16
+// mode): also the digit scale of every point, the least power of two not
+// below max_mu |phi_mu(r_i)| over the batch's functions (1 where all are
+// zero), kept as a running maximum in LDS (the bit patterns of non-negative
+// doubles order like unsigned integers) and written to the batch's scale row.
+template <typename T, bool SCALE>
 __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb,
                                                 const ReqDev* __restrict__ reqs,
                                                 char* __restrict__ scratch) {
@@ -233,11 +247,13 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
     const WaveBatch B = wb[blockIdx.x];
     const ReqG R = global_view(reqs[B.req]);
     __shared__ double sx[kMaxBatch], sy[kMaxBatch], sz[kMaxBatch];
+    __shared__ unsigned long long smax[SCALE ? kMaxBatch : 1];
     for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
         const bool v = i < B.ng;
         sx[i] = v ? R.px[B.pt_off + i] : 0.0;
         sy[i] = v ? R.py[B.pt_off + i] : 0.0;
         sz[i] = v ? R.pz[B.pt_off + i] : 0.0;
+        if (SCALE) smax[i] = 0ull;
     }
     __syncthreads();
     T* Phi = (T*)(scratch + 8 * B.phi_off);
@@ -256,12 +272,25 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
             if (i < B.ng) shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
             else rad = drad = 0.0;
             T* out = Phi + (size_t)loff * B.ngp + i;
+            double mx;
             switch (sh.L) {
-                case 0: phi_shell<0, T>(dx, dy, dz, rad, out, B.ngp); break;
-                case 1: phi_shell<1, T>(dx, dy, dz, rad, out, B.ngp); break;
-                case 2: phi_shell<2, T>(dx, dy, dz, rad, out, B.ngp); break;
-                default: phi_shell<3, T>(dx, dy, dz, rad, out, B.ngp); break;
+                case 0: mx = phi_shell<0, T>(dx, dy, dz, rad, out, B.ngp); break;
+                case 1: mx = phi_shell<1, T>(dx, dy, dz, rad, out, B.ngp); break;
+                case 2: mx = phi_shell<2, T>(dx, dy, dz, rad, out, B.ngp); break;
+                default: mx = phi_shell<3, T>(dx, dy, dz, rad, out, B.ngp); break;
             }
+            if (SCALE && mx > 0.0)
+                atomicMax(&smax[i], (unsigned long long)__double_as_longlong(mx));
+        }
+    }
+    if (SCALE) {
+        __syncthreads();
+        double* sc = (double*)(scratch + 8 * B.part_off) + scale_row_off(B);
+        for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
+            const double m = __longlong_as_double((long long)smax[i]);
+            int e = 0;
+            (void)frexp(m, &e);  // m = f 2^e with f in [0.5, 1), so m <= 2^e
+            sc[i] = m > 0.0 ? ldexp(1.0, max(e, -1000)) : 1.0;  // 1 / sc stays finite
         }
     }
 }
@@ -918,19 +947,19 @@ __global__ __launch_bounds__(256) void k_syr2k(
 }
 
 // ----------------------------------------------- split-BF16 contractions --
-// Each operand x is split when it is stored to LDS into bf16 parts
-// hi = bf16(x) and lo = bf16(x - hi), and each product a b is formed as
-// hi hi + hi lo + lo hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
-// (the lo lo term and what lies below the two parts are dropped: about 16
-// significant bits per product). Operand lane l of the MFMA holds
-// A[l % 16][8 (l / 16) + t] and B[8 (l / 16) + t][l % 16], t = 0..7; the
-// accumulator layout is FP32's (row 4 (l / 16) + r). Tiles are 64 x 64 with
-// K steps of 32, stored k-contiguous with a row pitch of 40 bf16 so that the
-// 16-byte fragment reads of 16 lanes fall in distinct banks.
+// Both contractions run on v_mfma_f32_16x16x32_bf16 (FP32 accumulation).
+// Operand lane l of the MFMA holds A[l % 16][8 (l / 16) + t] and
+// B[8 (l / 16) + t][l % 16], t = 0..7; the accumulator layout is FP32's (row
+// 4 (l / 16) + r). Tiles are 64 x 64 with K steps of 32, stored k-contiguous
+// in LDS with a row pitch of 40 bf16, so that the 16-byte fragment reads of
+// 16 lanes fall in distinct banks.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kKB = 32;        // K step of the split-BF16 kernels
 constexpr int kBP = kKB + 8;   // LDS row pitch in bf16
 
+// Potential contraction: x = hi + lo with hi = bf16(x), lo = bf16(x - hi),
+// and a b ~ hi hi + hi lo + lo hi (the lo lo term and what lies below the
+// two parts are dropped: about 16 significant bits per product).
 __device__ inline void split_bf16(double x, __bf16& h, __bf16& l) {
     h = (__bf16)(float)x;
     l = (__bf16)(float)(x - (double)(float)h);
@@ -944,24 +973,97 @@ __device__ inline v4f mfma_bf16x3(const bf16x8& ah, const bf16x8& al, const bf16
     return c;
 }
 
-// Density contraction X = P^j Phi^j in split BF16 (Phi stored in FP32), the
-// same tiles, gather and epilogue as k_gemm_rho.
+// Density contraction: exact digit products. A value y with |y| <= 1 (an
+// entry of P over its row's scale, or of Phi over its point's scale, both
+// powers of two) is cut into four digits d0 = rint(128 y), then
+// d_u = rint(256 r) with r the remainder scaled by the previous step; every
+// digit is an integer of magnitude <= 128 (exact in BF16), every subtraction
+// is exact (its operands lie within a factor of two, or the digit is zero),
+// and y = sum_u d_u 2^{-7-8u} up to a remainder below 2^{-32}. A product of
+// two digits is an integer below 2^14 in magnitude and a sum of 2^10 of them
+// stays below 2^24, so FP32 accumulation of digit products is exact however
+// the hardware orders it. The products of digit orders u + v = g (g <= 3,
+// ten products per pair of entries) share one accumulator of weight
+// 2^{-14-8g}; every four K steps (128 terms, at most 4 x 128 products of
+// 2^14, below 2^24) the accumulators are added into FP64 and cleared.
+__device__ inline void digits4(double y, __bf16 (&d)[4]) {
+    double a = y * 128.0;
+    double q = rint(a);
+    d[0] = (__bf16)(float)q;
+#pragma unroll
+    for (int u = 1; u < 4; ++u) {
+        a = (a - q) * 256.0;
+        q = rint(a);
+        d[u] = (__bf16)(float)q;
+    }
+}
+
+__device__ inline unsigned short bf16_bits(__bf16 v) {
+    return __builtin_bit_cast(unsigned short, v);
+}
+__device__ inline __bf16 bits_bf16(unsigned short v) {
+    return __builtin_bit_cast(__bf16, v);
+}
+
+// Digits of P, one workgroup per row mu: the row scale s_mu is the least
+// power of two not below max_nu |P_mu nu| (1 for a zero row), and entry
+// (mu, nu) is stored as its four digits of P_mu nu / s_mu packed in 64 bits
+// (digit u in bits 16 u .. 16 u + 15).
+__global__ __launch_bounds__(256) void k_p_digits(const double* __restrict__ P, int nbf,
+                                                  unsigned long long* __restrict__ dig,
+                                                  double* __restrict__ scale) {
+    const int mu = blockIdx.x;
+    const double* row = P + (size_t)mu * nbf;
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int nu = threadIdx.x; nu < nbf; nu += blockDim.x) m = fmax(m, fabs(row[nu]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    const double mx = red[0];
+    int e = 0;
+    (void)frexp(mx, &e);
+    e = max(e, -1000);  // 1 / scale stays finite
+    const double sc = mx > 0.0 ? ldexp(1.0, e) : 1.0;
+    const double inv = mx > 0.0 ? ldexp(1.0, -e) : 1.0;
+    if (threadIdx.x == 0) scale[mu] = sc;
+    unsigned long long* drow = dig + (size_t)mu * nbf;
+    for (int nu = threadIdx.x; nu < nbf; nu += blockDim.x) {
+        __bf16 d[4];
+        digits4(row[nu] * inv, d);
+        unsigned long long w = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w |= (unsigned long long)bf16_bits(d[u]) << (16 * u);
+        drow[nu] = w;
+    }
+}
+
+// X = P^j Phi^j from digits: X[mu][i] = s_mu s_i 2^{-14}
+// sum_{u+v<=3} 2^{-8(u+v)} sum_nu dP_u[mu][nu] dPhi_v[nu][i], with the digits
+// of P gathered from the precomputed array through the batch's function list
+// and those of Phi cut from the FP64 slab as it is staged (per-point scales
+// from the collocation kernel). Same tiles and epilogue as k_gemm_rho; one
+// LDS buffer (eight digit planes, 40 KB) with the next step's loads in
+// registers.
 template <bool GGA>
-__global__ __launch_bounds__(256) void k_gemm_rho_bf16(
+__global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
     const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
     const int t = xcd_remap(blockIdx.x, ntiles);
     const int2 tb = tmap[t];
     const WaveBatch B = wb[tb.x];
     const ReqG R = global_view(reqs[B.req]);
-    const gptr<const double> P = R.P;
     const int nbf = R.nbf;
     const int lt = tb.y;
     const int ntn = B.ngp / kTile;
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
     exp_table_init();
-    const float* Phi = (const float*)(scratch + 8 * B.phi_off);
+    const double* Phi = (const double*)(scratch + 8 * B.phi_off);
+    const double* pscale = (const double*)(scratch + 8 * B.part_off) + scale_row_off(B);
     const gptr<const int> fl = R.func_list + B.func_off;
     // the epilogue's point (one per lane), loaded now so that its latency hides
     const bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
@@ -973,14 +1075,12 @@ __global__ __launch_bounds__(256) void k_gemm_rho_bf16(
         ez = R.pz[pi];
     }
 
-    // four operand tiles (A, B) x (hi, lo), double-buffered; X in the epilogue
-    constexpr int kOpBytes = kTile * kBP * 2;
-    constexpr int kLds = 8 * kOpBytes;
-    static_assert(kLds >= kTile * (kTile + 1) * 8, "the X tile fits in the operand space");
-    __shared__ __attribute__((aligned(16))) char lds[kLds];
-    auto tile = [&](int which, int buf) {
-        return reinterpret_cast<__bf16 (*)[kBP]>(lds + (which * 2 + buf) * kOpBytes);
-    };
+    // digit planes 0-3 of the A tile (rows of P^j), 4-7 of the B tile (points)
+    constexpr int kPlaneBytes = kTile * kBP * 2;
+    constexpr int kOpBytes = 8 * kPlaneBytes;
+    constexpr int kXBytes = kTile * (kTile + 1) * 8;
+    __shared__ __attribute__((aligned(16))) char lds[kOpBytes > kXBytes ? kOpBytes : kXBytes];
+    auto plane = [&](int p) { return reinterpret_cast<__bf16 (*)[kBP]>(lds + p * kPlaneBytes); };
     double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
     __shared__ int frow[kTile], fsh[kTile];
     __shared__ __attribute__((aligned(16))) int sfl[2][kKB];
@@ -1012,117 +1112,150 @@ __global__ __launch_bounds__(256) void k_gemm_rho_bf16(
     }
     __syncthreads();
 
-    // thread: row (function) or column (point) tid / 4, K offset 8 (tid % 4)
+    // A: row tid / 4 and K offset 8 (tid % 4); B: point tid % 64 and K offset
+    // 8 (tid / 64), so that a wave's Phi loads are 64 consecutive points
     const int ar = tid >> 2, ak = (tid & 3) * 8;
+    const int bn = tid & 63, bk = (tid >> 6) * 8;
     const int fr = frow[ar];
-    const gptr<const double> Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
+    const gptr<const unsigned long long> Prow = R.Pdig + (size_t)(fr >= 0 ? fr : 0) * nbf;
+    const double inv_sn = 1.0 / pscale[n0 + bn];   // a power of two: exact
     int fc[8];
-    double pv[8];
-    float bv[8];
-    auto fread = [&](int ks) {
+    unsigned long long pa[8];
+    double pb[8];
+    auto gload = [&](int ks) {
         const int4 u = *reinterpret_cast<const int4*>(&sfl[ks & 1][ak]);
         const int4 v = *reinterpret_cast<const int4*>(&sfl[ks & 1][ak + 4]);
         fc[0] = u.x; fc[1] = u.y; fc[2] = u.z; fc[3] = u.w;
         fc[4] = v.x; fc[5] = v.y; fc[6] = v.z; fc[7] = v.w;
-    };
-    // loads go to valid (clamped) addresses; padding is zeroed at the store
-    auto gload = [&](int ks) {
+        // loads go to valid (clamped) addresses; padding is zeroed at the store
 #pragma unroll
-        for (int q = 0; q < 8; ++q) pv[q] = Prow[fc[q] >= 0 ? fc[q] : 0];
-        const int kb = ks * kKB + ak;
+        for (int q = 0; q < 8; ++q) pa[q] = Prow[fc[q] >= 0 ? fc[q] : 0];
+        const int kb = ks * kKB + bk;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = kb + q;
-            bv[q] = Phi[(size_t)(k < B.nbp ? k : 0) * B.ngp + n0 + ar];
+            pb[q] = Phi[(size_t)(k < B.nbp ? k : 0) * B.ngp + n0 + bn];
         }
     };
-    auto sstore = [&](int buf, int ks) {
-        bf16x8 h, l;
+    auto sstore = [&](int ks) {
+        bf16x8 d[4];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            __bf16 hq, lq;
-            split_bf16((fr >= 0 && fc[q] >= 0) ? pv[q] : 0.0, hq, lq);
-            h[q] = hq;
-            l[q] = lq;
+            const unsigned long long w = (fr >= 0 && fc[q] >= 0) ? pa[q] : 0ull;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[u][q] = bits_bf16((unsigned short)(w >> (16 * u)));
         }
-        *reinterpret_cast<bf16x8*>(&tile(0, buf)[ar][ak]) = h;
-        *reinterpret_cast<bf16x8*>(&tile(1, buf)[ar][ak]) = l;
-        const int kb = ks * kKB + ak;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) *reinterpret_cast<bf16x8*>(&plane(u)[ar][ak]) = d[u];
+        const int kb = ks * kKB + bk;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            __bf16 hq, lq;
-            split_bf16(kb + q < B.nbp ? (double)bv[q] : 0.0, hq, lq);
-            h[q] = hq;
-            l[q] = lq;
+            __bf16 e4[4];
+            digits4(kb + q < B.nbp ? pb[q] * inv_sn : 0.0, e4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[u][q] = e4[u];
         }
-        *reinterpret_cast<bf16x8*>(&tile(2, buf)[ar][ak]) = h;
-        *reinterpret_cast<bf16x8*>(&tile(3, buf)[ar][ak]) = l;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) *reinterpret_cast<bf16x8*>(&plane(4 + u)[bn][bk]) = d[u];
     };
 
-    v4f acc[2][2];
+    v4f acc[4][2][2];
+    v4d acc64[2][2];
     bool live[2][2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-            acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int g = 0; g < 4; ++g) acc[g][mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+            acc64[mb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
             live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + wn * 32 + nb * 16 < B.ng);
         }
-
-    fread(0);
-    gload(0);
-    sstore(0, 0);
-    if (nk > 2) fetch(2);
-    __syncthreads();
-    const int fk = 8 * (lane >> 4);
-    for (int ks = 0; ks < nk; ++ks) {
-        const int cur = ks & 1;
-        if (ks + 1 < nk) {
-            fread(ks + 1);
-            gload(ks + 1);
-        }
-        bf16x8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const int r = wm * 32 + mb * 16 + (lane & 15);
-            ah[mb] = *reinterpret_cast<const bf16x8*>(&tile(0, cur)[r][fk]);
-            al[mb] = *reinterpret_cast<const bf16x8*>(&tile(1, cur)[r][fk]);
-        }
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            const int cc = wn * 32 + nb * 16 + (lane & 15);
-            bh[nb] = *reinterpret_cast<const bf16x8*>(&tile(2, cur)[cc][fk]);
-            bl[nb] = *reinterpret_cast<const bf16x8*>(&tile(3, cur)[cc][fk]);
-        }
+    auto flush = [&]() {
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb)
-                if (live[mb][nb])
-                    acc[mb][nb] = mfma_bf16x3(ah[mb], al[mb], bh[nb], bl[nb], acc[mb][nb]);
-        if (ks + 1 < nk) sstore(cur ^ 1, ks + 1);
-        if (ks + 2 < nk) {
-            fput(ks & 1);
-            if (ks + 3 < nk) fetch(ks + 3);
-        }
-        __syncthreads();
-    }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = (double)acc[3][mb][nb][r];
+                    v = fma(v, 0x1p-8, (double)acc[2][mb][nb][r]);
+                    v = fma(v, 0x1p-8, (double)acc[1][mb][nb][r]);
+                    v = fma(v, 0x1p-8, (double)acc[0][mb][nb][r]);
+                    acc64[mb][nb][r] += v;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) acc[g][mb][nb][r] = 0.f;
+                }
+    };
 
+    gload(0);
+    sstore(0);
+    if (nk > 2) fetch(2);
+    __syncthreads();
+    const int fk = 8 * (lane >> 4);
+    for (int ks = 0; ks < nk; ++ks) {
+        if (ks + 1 < nk) gload(ks + 1);
+        bf16x8 b[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+                b[u][nb] = *reinterpret_cast<const bf16x8*>(
+                    &plane(4 + u)[wn * 32 + nb * 16 + (lane & 15)][fk]);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            bf16x8 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                a[u] = *reinterpret_cast<const bf16x8*>(
+                    &plane(u)[wm * 32 + mb * 16 + (lane & 15)][fk]);
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                if (!live[mb][nb]) continue;
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int u = 0; u <= g; ++u)
+                        acc[g][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a[u], b[g - u][nb], acc[g][mb][nb], 0, 0, 0);
+            }
+        }
+        if ((ks & 3) == 3) flush();
+        __syncthreads();
+        if (ks + 1 < nk) {
+            sstore(ks + 1);
+            if (ks + 2 < nk) {
+                fput(ks & 1);
+                if (ks + 3 < nk) fetch(ks + 3);
+            }
+            __syncthreads();
+        }
+    }
+    flush();
+
+    // X = acc64 2^{-14} s_mu s_i (the loop ended on a barrier, so the operand
+    // planes are free for the X tile)
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int nb = 0; nb < 2; ++nb) {
+            const int tc = wn * 32 + nb * 16 + (lane & 15);
+            const double sn = pscale[n0 + tc] * 0x1p-14;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                Xs[wm * 32 + mb * 16 + 4 * (lane >> 4) + r][wn * 32 + nb * 16 + (lane & 15)] =
-                    double(acc[mb][nb][r]);
+            for (int r = 0; r < 4; ++r) {
+                const int tr = wm * 32 + mb * 16 + 4 * (lane >> 4) + r;
+                const int f = frow[tr];
+                const double sm = f >= 0 ? R.Pscale[f] : 0.0;
+                Xs[tr][tc] = acc64[mb][nb][r] * sm * sn;
+            }
+        }
     __syncthreads();
     rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, frow, ex, ey, ez, has, scratch);
 }
 
-// Potential contraction V^j = Z Phi^T + Phi Z^T in split BF16 (Phi and Z
-// stored in FP32), lower-triangle tiles as in k_syr2k (diagonal tiles reuse
-// their row operands), one LDS buffer with the next step's loads in
+// Potential contraction V^j = Z Phi^T + Phi Z^T in split BF16 (Phi stored
+// in FP64, Z in FP32), lower-triangle tiles as in k_syr2k (diagonal tiles
+// reuse their row operands), one LDS buffer with the next step's loads in
 // registers.
 __global__ __launch_bounds__(256) void k_syr2k_bf16(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
@@ -1140,7 +1273,7 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     while (I * (I + 1) / 2 > lt) --I;
     const int J = lt - I * (I + 1) / 2;
     const size_t slab = (size_t)B.nbp * B.ngp;
-    const float* Phi = (const float*)(scratch + 8 * B.phi_off);
+    const double* Phi = (const double*)(scratch + 8 * B.phi_off);
     const float* Zm = (const float*)(scratch + 8 * (B.phi_off + (long long)slab));
     const gptr<const int> fl = func_list + B.func_off;
 
@@ -1165,37 +1298,49 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     const int lr = tid >> 2, lk = (tid & 3) * 8;
     const int rI = I * kTile + lr, rJ = J * kTile + lr;
     const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
-    const float* src[4] = {Zm + (size_t)(vI ? rI : 0) * B.ngp, Phi + (size_t)(vI ? rI : 0) * B.ngp,
-                           Phi + (size_t)(vJ ? rJ : 0) * B.ngp, Zm + (size_t)(vJ ? rJ : 0) * B.ngp};
-    const bool valid[4] = {vI, vI, vJ, vJ};
+    // operand a: 0 = Z_I, 1 = Phi_I, 2 = Phi_J, 3 = Z_J
+    const float* zsrc[2] = {Zm + (size_t)(vI ? rI : 0) * B.ngp, Zm + (size_t)(vJ ? rJ : 0) * B.ngp};
+    const double* psrc[2] = {Phi + (size_t)(vI ? rI : 0) * B.ngp,
+                             Phi + (size_t)(vJ ? rJ : 0) * B.ngp};
     // a diagonal tile's column operands are its row operands
     const bool diag = I == J;
-    float4 g[4][2];
+    float4 gz[2][2];
+    double2 gp[2][4];
     auto gload = [&](int ks) {
         const int k0 = ks * kKB + lk;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            if (a >= 2 && diag) continue;
-            g[a][0] = *reinterpret_cast<const float4*>(src[a] + k0);
-            g[a][1] = *reinterpret_cast<const float4*>(src[a] + k0 + 4);
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && diag) continue;
+            gz[h][0] = *reinterpret_cast<const float4*>(zsrc[h] + k0);
+            gz[h][1] = *reinterpret_cast<const float4*>(zsrc[h] + k0 + 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                gp[h][q] = *reinterpret_cast<const double2*>(psrc[h] + k0 + 2 * q);
         }
+    };
+    auto put = [&](int which, const double (&x)[8], bool valid) {
+        bf16x8 hv, lv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            __bf16 hq, lq;
+            split_bf16(valid ? x[q] : 0.0, hq, lq);
+            hv[q] = hq;
+            lv[q] = lq;
+        }
+        *reinterpret_cast<bf16x8*>(&tile(which)[lr][lk]) = hv;
+        *reinterpret_cast<bf16x8*>(&tile(which + 1)[lr][lk]) = lv;
     };
     auto sstore = [&]() {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            if (a >= 2 && diag) continue;
-            const float x[8] = {g[a][0].x, g[a][0].y, g[a][0].z, g[a][0].w,
-                                g[a][1].x, g[a][1].y, g[a][1].z, g[a][1].w};
-            bf16x8 h, l;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                __bf16 hq, lq;
-                split_bf16(valid[a] ? (double)x[q] : 0.0, hq, lq);
-                h[q] = hq;
-                l[q] = lq;
-            }
-            *reinterpret_cast<bf16x8*>(&tile(2 * a)[lr][lk]) = h;
-            *reinterpret_cast<bf16x8*>(&tile(2 * a + 1)[lr][lk]) = l;
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && diag) continue;
+            const bool valid = h == 0 ? vI : vJ;
+            const double z[8] = {gz[h][0].x, gz[h][0].y, gz[h][0].z, gz[h][0].w,
+                                 gz[h][1].x, gz[h][1].y, gz[h][1].z, gz[h][1].w};
+            const double p[8] = {gp[h][0].x, gp[h][0].y, gp[h][1].x, gp[h][1].y,
+                                 gp[h][2].x, gp[h][2].y, gp[h][3].x, gp[h][3].y};
+            put(h == 0 ? 0 : 6, z, valid);
+            put(h == 0 ? 2 : 4, p, valid);
         }
     };
 
@@ -1337,7 +1482,7 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                          bool colloc) {
     if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
-        hipLaunchKernelGGL((k_colloc<T>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        hipLaunchKernelGGL((k_colloc<T, false>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (gemm_tiles > 0) {
@@ -1368,7 +1513,8 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
     return XC_OK;
 }
 
-// Split-BF16 mode: Phi and Z stored in FP32, both contractions split BF16.
+// Split-BF16 mode: Phi stored in FP64 with per-point digit scales, Z in
+// FP32, both contractions on BF16 MFMA.
 template <bool GGA>
 static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                             const int* gpre, const int* spre, int count, int gemm_tiles,
@@ -1376,7 +1522,7 @@ static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b
                             bool colloc) {
     if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
-        hipLaunchKernelGGL((k_colloc<float>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        hipLaunchKernelGGL((k_colloc<double, true>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (gemm_tiles > 0) {
@@ -1418,7 +1564,7 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
     if (precision == XC_MIXED_FP32)
         return gga ? launch_wave_t<true, float, float>(XC_WAVE_ARGS)
                    : launch_wave_t<false, float, float>(XC_WAVE_ARGS);
-    if (precision == XC_MIXED_BF16X3)
+    if (precision == XC_MIXED_BF16)
         return gga ? launch_wave_bf16<true>(XC_WAVE_ARGS) : launch_wave_bf16<false>(XC_WAVE_ARGS);
     if (precision == XC_MIXED_FP32_V)
         return gga ? launch_wave_t<true, double, float>(XC_WAVE_ARGS)
@@ -1428,8 +1574,18 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
 #undef XC_WAVE_ARGS
 }
 
-int phi_elem_bytes(int precision) {
-    return (precision == XC_MIXED_FP32 || precision == XC_MIXED_BF16X3) ? 4 : 8;
+int phi_kind(int precision) {
+    if (precision == XC_MIXED_FP32) return 2;
+    if (precision == XC_MIXED_BF16) return 3;
+    return 1;
+}
+
+int launch_p_digits(hipStream_t s, const double* P, int nbf, unsigned long long* dig,
+                    double* scale) {
+    if (nbf <= 0) return XC_OK;
+    hipLaunchKernelGGL(k_p_digits, dim3(nbf), dim3(256), 0, s, P, nbf, dig, scale);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
 }
 
 int launch_finish(PhaseTimer* timer, hipStream_t s, double* dV, int nbf,
@@ -1477,6 +1633,8 @@ ReqDev make_req(const xc_context* c, const double* dP, double* dV) {
     r.epart = (double*)c->epart.p;
     r.npart = (double*)c->npart.p;
     r.func_shell = (const int*)c->d_fshell.p;
+    r.Pdig = (const unsigned long long*)c->pdig.p;
+    r.Pscale = (const double*)c->pscale.p;
     r.rho_thresh = c->rho_thresh;
     r.nbf = c->nbf;
     return r;
@@ -1491,6 +1649,12 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
         hipLaunchKernelGGL(k_fill, dim3(grid_1d(nn, 256)), dim3(256), 0, c->stream, dV, nn, 0.0);
         XC_HIP(hipGetLastError());
     }
+    if (precision == XC_MIXED_BF16) {
+        XC_TRY(dev_reserve(c->pdig, 8 * (size_t)c->nbf * c->nbf));
+        XC_TRY(dev_reserve(c->pscale, 8 * (size_t)c->nbf));
+        XC_TRY(launch_p_digits(c->stream, dP, c->nbf, (unsigned long long*)c->pdig.p,
+                               (double*)c->pscale.p));
+    }
     XC_TRY(dev_reserve(c->d_req, sizeof(ReqDev)));
     XC_TRY(launch_put_req(c->stream, (ReqDev*)c->d_req.p, make_req(c, dP, dV)));
     const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
@@ -1499,16 +1663,16 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
     // With one wave the scratch still holds the previous integration's Phi
     // (no later kernel writes its slab), so a cached Phi of the same storage
     // type is used as it stands.
-    const int esz = phi_elem_bytes(precision);
+    const int kind = phi_kind(precision);
     const bool cacheable = c->phi_cache && !c->external_scratch && c->waves.size() == 1;
-    const bool colloc = !(cacheable && c->phi_cached_bytes == esz);
-    c->phi_cached_bytes = 0;
+    const bool colloc = !(cacheable && c->phi_cached_kind == kind);
+    c->phi_cached_kind = 0;
     for (const Wave& w : c->waves)
         XC_TRY(launch_wave(&c->timer, c->stream, gga, precision, wb + w.wb_off,
                            gpre + w.pre_off, spre + w.pre_off, w.count, w.gemm_tiles,
                            w.syr_tiles, (const ReqDev*)c->d_req.p, (char*)c->scratch.p,
                            (int*)c->d_tmap.p, colloc));
-    if (cacheable) c->phi_cached_bytes = esz;
+    if (cacheable) c->phi_cached_kind = kind;
     return launch_finish(&c->timer, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);
 }

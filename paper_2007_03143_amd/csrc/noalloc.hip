@@ -48,9 +48,13 @@ int run_integrate_noalloc(xc_context* c, int functional, int precision, const do
     XC_HIP(hipGetDevice(&dev));
     if (dev != c->device)
         return fail(XC_ERR_STATE, "the context's device is not the current device");
-    // layout: request descriptor | tile map of the largest wave | wave scratch
+    // layout: request descriptor | tile map of the largest wave | (split-BF16
+    // mode) digits and row scales of P | wave scratch
+    const bool bf16 = precision == XC_MIXED_BF16;
     const size_t tmap_bytes = round256(2 * sizeof(int) * (size_t)c->max_tiles);
-    const size_t need = kReqBytes + tmap_bytes + c->max_wave_bytes;
+    const size_t dig_bytes = bf16 ? round256(8 * (size_t)c->nbf * c->nbf) : 0;
+    const size_t scl_bytes = bf16 ? round256(8 * (size_t)c->nbf) : 0;
+    const size_t need = kReqBytes + tmap_bytes + dig_bytes + scl_bytes + c->max_wave_bytes;
     if (need > kStaticScratchBytes)
         return fail(XC_ERR_NOMEM,
                     "the context's largest wave needs " + std::to_string(need) +
@@ -61,11 +65,19 @@ int run_integrate_noalloc(xc_context* c, int functional, int precision, const do
     XC_TRY(static_scratch(dev, &base));
     ReqDev* d_req = (ReqDev*)base;
     int* d_tmap = (int*)(base + kReqBytes);
-    char* wave_scratch = base + kReqBytes + tmap_bytes;
+    unsigned long long* d_dig = (unsigned long long*)(base + kReqBytes + tmap_bytes);
+    double* d_scl = (double*)(base + kReqBytes + tmap_bytes + dig_bytes);
+    char* wave_scratch = base + kReqBytes + tmap_bytes + dig_bytes + scl_bytes;
 
     const bool gga = functional == XC_GGA_PBE;
     XC_TRY(launch_fill(c->stream, dV, (long long)c->nbf * c->nbf, 0.0));
-    XC_TRY(launch_put_req(c->stream, d_req, make_req(c, dP, dV)));
+    ReqDev req = make_req(c, dP, dV);
+    if (bf16) {
+        XC_TRY(launch_p_digits(c->stream, dP, c->nbf, d_dig, d_scl));
+        req.Pdig = d_dig;
+        req.Pscale = d_scl;
+    }
+    XC_TRY(launch_put_req(c->stream, d_req, req));
     const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
     const int* gpre = (const int*)c->d_gemm_pre.p;
     const int* spre = (const int*)c->d_syr_pre.p;

@@ -81,10 +81,16 @@ struct WaveBatch {
     int req;            // index of the request descriptor (ReqDev) of the launch
 };
 
-// Wave-scratch bytes of one batch: Phi and Z slabs plus the density
-// partials (four per row tile and padded point).
+// Wave-scratch bytes of one batch: Phi and Z slabs, the density partials
+// (four per row tile and padded point), then one row of per-point digit
+// scales (split-BF16 mode).
 inline size_t batch_scratch_bytes(const WaveBatch& w) {
-    return 8 * (kSlabs * (size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
+    return 8 * (kSlabs * (size_t)w.nbp * w.ngp + ((size_t)w.nmt * 4 + 1) * w.ngp);
+}
+
+// Offset (doubles, from the batch's partials) of its per-point digit scales.
+__host__ __device__ inline long long scale_row_off(const WaveBatch& w) {
+    return (long long)w.nmt * 4 * w.ngp;
 }
 
 // Larger of the batch's density-GEMM and potential-SYR2K tile counts.
@@ -111,6 +117,8 @@ struct ReqDev {
     double* V;
     double* epart;
     double* npart;
+    const unsigned long long* Pdig;  // split-BF16 mode: four BF16 digits per entry of P
+    const double* Pscale;            // and the power-of-two scale of each row of P
     double rho_thresh;
     int nbf;
     int pad_;
@@ -193,9 +201,10 @@ struct xc_context {
     int max_tiles = 1;           // most tiles of one contraction launch in any wave
     xc::DevBuf epart, npart;
     xc::DevBuf d_req;            // one ReqDev for the context's own integrations
+    xc::DevBuf pdig, pscale;     // digits and row scales of P (split-BF16 mode)
     bool external_scratch = false;  // wave scratch supplied by an engine
     bool phi_cache = false;         // keep Phi in the scratch between integrations
-    int phi_cached_bytes = 0;       // element size of the Phi the scratch holds; 0: none
+    int phi_cached_kind = 0;        // phi_kind() of the Phi the scratch holds; 0: none
 
     xc::PhaseTimer timer;
 
@@ -266,8 +275,12 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
 // descriptor in the library's static device array (no allocation).
 int run_integrate_noalloc(xc_context* c, int functional, int precision, const double* dP,
                           double* dV, double* dEN);
-// Bytes per element of the stored Phi under a precision code.
-int phi_elem_bytes(int precision);
+// What the collocation kernel stores under a precision code: 1 Phi in FP64,
+// 2 Phi in FP32, 3 Phi in FP64 with per-point digit scales (split BF16).
+int phi_kind(int precision);
+// Split-BF16 digits and row scales of the nbf x nbf density matrix P.
+int launch_p_digits(hipStream_t s, const double* P, int nbf, unsigned long long* dig,
+                    double* scale);
 // Fill n doubles with v (a kernel, so it can be captured in a graph).
 int launch_fill(hipStream_t s, double* p, long long n, double v);
 // V mirror and the fixed-order E_xc / N_e sums of one finished integration.

@@ -69,7 +69,7 @@ def test_engine_mixed_precisions_and_oracle():
     reqs = _requests(n=4, n_iter=2)
     reqs[1].precision = "fp32"
     reqs[2].precision = "fp32v"
-    reqs[3].precision = "bf16x3"
+    reqs[3].precision = "bf16"
     ref = [_alone(r) for r in reqs]
     serve(reqs, wave_bytes=8 << 20, keep_v=lambda i: True)
     for r, rr in zip(reqs, ref):

@@ -37,7 +37,7 @@ def _both(w, functional, precision, wave_bytes):
 
 
 @pytest.mark.parametrize("functional,precision", [("pbe", "fp64"), ("lda", "fp64"),
-                                                  ("pbe", "fp32")])
+                                                  ("pbe", "fp32"), ("pbe", "bf16")])
 def test_noalloc_matches_context_entry(functional, precision):
     from workloads import cfg_water, cfg_water_cluster
     big = cfg_water_cluster(4, functional=functional, n_rad=40, n_ang=110, seed=11)

@@ -47,10 +47,27 @@ class BasisSet:
     shell_nprim: np.ndarray   # int32 [nshells]
     prim_alpha: np.ndarray    # float64 [sum nprim], packed in shell order
     prim_coef: np.ndarray     # float64 [sum nprim]
+    # int32 [nshells] or None: 1 marks a shell of L >= 2 whose functions are
+    # the 2L+1 real solid harmonics instead of the Cartesian components
+    # (L <= 1 shells stay Cartesian whatever the flag says)
+    shell_pure: np.ndarray = None
 
     @property
     def nshells(self):
         return int(self.shell_L.shape[0])
+
+    def is_pure(self, s):
+        return (self.shell_pure is not None and bool(self.shell_pure[s])
+                and int(self.shell_L[s]) >= 2)
+
+    @property
+    def any_pure(self):
+        return any(self.is_pure(s) for s in range(self.nshells))
+
+    def cartesian(self):
+        """The same shells with every function Cartesian."""
+        return BasisSet(self.shell_atom, self.shell_L, self.shell_nprim, self.prim_alpha,
+                        self.prim_coef)
 
     @property
     def prim_offset(self):
@@ -60,7 +77,8 @@ class BasisSet:
 
     @property
     def shell_nfunc(self):
-        return np.array([n_cart(int(L)) for L in self.shell_L], dtype=np.int64)
+        return np.array([2 * int(L) + 1 if self.is_pure(s) else n_cart(int(L))
+                         for s, L in enumerate(self.shell_L)], dtype=np.int64)
 
     @property
     def first_func(self):
@@ -138,8 +156,10 @@ def element_shells(Z, seed, diffuse=None, polarisation=False):
     return out
 
 
-def make_basis(Z, seed=2007, diffuse=None, polarisation=False):
-    """Basis for a molecule with atomic numbers Z (shells in atom order)."""
+def make_basis(Z, seed=2007, diffuse=None, polarisation=False, pure=False):
+    """Basis for a molecule with atomic numbers Z (shells in atom order).
+    pure=True marks every shell spherical (2L+1 real solid harmonics for
+    L >= 2), as in the correlation-consistent basis sets."""
     atom, Ls, npr, al, co = [], [], [], [], []
     cache = {}
     for a, z in enumerate(Z):
@@ -155,7 +175,8 @@ def make_basis(Z, seed=2007, diffuse=None, polarisation=False):
     return BasisSet(np.array(atom, dtype=np.int32), np.array(Ls, dtype=np.int32),
                     np.array(npr, dtype=np.int32),
                     np.ascontiguousarray(np.concatenate(al)),
-                    np.ascontiguousarray(np.concatenate(co)))
+                    np.ascontiguousarray(np.concatenate(co)),
+                    np.ones(len(Ls), dtype=np.int32) if pure else None)
 
 
 # --- analytic overlap ------------------------------------------------------
@@ -167,7 +188,11 @@ def _moment(t, p):
 
 
 def overlap_matrix(basis, coords, chunk=200000):
-    """Analytic overlap S of the Cartesian basis at atom coordinates coords."""
+    """Analytic overlap S of the Cartesian basis at atom coordinates coords.
+    A basis with spherical shells is refused (use basis.cartesian() for the
+    overlap of the Cartesian functions the shells are built from)."""
+    if basis.any_pure:
+        raise ValueError("overlap_matrix covers Cartesian shells only")
     nb = basis.nbf
     S = np.zeros((nb, nb))
     ff = basis.first_func

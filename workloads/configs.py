@@ -12,7 +12,7 @@ import numpy as np
 
 from .angular import lebedev_table
 from .basis import BasisSet, make_basis, overlap_matrix
-from .density import random_density, perturbed_density
+from .density import random_density, perturbed_density, random_psd_density
 from .molecules import Molecule, water, water_cluster, peptide_chain
 
 # Mura-Knowles radial scale per element (5.0 for H, C, N, O).
@@ -70,20 +70,28 @@ def grid_spec_dict(w, atom_mask=None, **over):
 
 
 def _finish(name, mol, n_occ, n_rad, n_ang, functional, seed, diffuse=None,
-            with_S=True, polarisation=False):
-    basis = make_basis(mol.Z, seed=2007, diffuse=diffuse, polarisation=polarisation)
+            with_S=True, polarisation=False, pure=False):
+    basis = make_basis(mol.Z, seed=2007, diffuse=diffuse, polarisation=polarisation,
+                       pure=pure)
+    if pure:
+        # the generators form Cartesian overlaps only: a plain PSD density
+        P = random_psd_density(basis.nbf, n_occ, seed=seed)
+        return Workload(name, mol, basis, P, n_occ, n_rad, n_ang, functional)
     S = overlap_matrix(basis, mol.coords)
     P = random_density(S, n_occ, seed=seed)
     return Workload(name, mol, basis, P, n_occ, n_rad, n_ang, functional,
                     S=S if with_S else None)
 
 
-def cfg_water(functional="lda", n_rad=75, n_ang=302, seed=1, polarisation=False):
+def cfg_water(functional="lda", n_rad=75, n_ang=302, seed=1, polarisation=False,
+              pure=False):
     """One water, ~25 functions, 5 occupied orbitals (tr PS = 10),
     75 x 302 grid per atom (67,950 points). polarisation=True adds an f
-    shell on O and a d shell on each H (47 functions)."""
-    return _finish("water_fd" if polarisation else "water", water(), 5, n_rad, n_ang,
-                   functional, seed, polarisation=polarisation)
+    shell on O and a d shell on each H (47 functions); pure=True makes the
+    d and f shells spherical (41 functions with polarisation)."""
+    name = "water_fd" if polarisation else "water"
+    return _finish(name + ("_sph" if pure else ""), water(), 5, n_rad, n_ang,
+                   functional, seed, polarisation=polarisation, pure=pure)
 
 
 def cfg_water_cluster(n_waters=64, functional="pbe", n_rad=100, n_ang=590,

@@ -25,3 +25,13 @@ def perturbed_density(P0, norm, seed):
     d = 0.5 * (d + d.T)
     d *= norm / np.linalg.norm(d)
     return np.ascontiguousarray(P0 + d)
+
+
+def random_psd_density(nbf, n_occ, seed=0):
+    """P = 2 C C^T / nbf with C (nbf x n_occ) standard normal: symmetric
+    positive semidefinite, without reference to an overlap matrix (for bases
+    whose overlap the generators do not form)."""
+    rng = np.random.default_rng([seed, 3])
+    C = rng.normal(size=(nbf, n_occ))
+    P = 2.0 * C @ C.T / nbf
+    return np.ascontiguousarray(0.5 * (P + P.T))

@@ -30,7 +30,8 @@ the internal properties listed in the tests (limits, special cases,
 symbolic derivatives, V = dE/dP by finite differences).
 """
 from .quadrature import mura_knowles, atomic_grid, molecular_grid
-from .partition import ssf_cell, ssf_partition, ssf_weights
+from .partition import (ssf_cell, ssf_partition, ssf_weights, becke_cell,
+                        becke_size_adjustment, becke_partition, becke_weights)
 from .basis import cart_exponents, shell_rcut, collocation
 from .screening import cuboid_sphere_intersect, screen_batch
 from .functionals import slater, vwn5, pbe_x, pbe_c, evaluate
@@ -38,7 +39,8 @@ from .integrate import integrate, density_on_points, grid_and_weights
 
 __all__ = [
     "mura_knowles", "atomic_grid", "molecular_grid", "ssf_cell",
-    "ssf_partition", "ssf_weights", "cart_exponents", "shell_rcut",
+    "ssf_partition", "ssf_weights", "becke_cell", "becke_size_adjustment",
+    "becke_partition", "becke_weights", "cart_exponents", "shell_rcut",
     "collocation", "cuboid_sphere_intersect", "screen_batch", "slater",
     "vwn5", "pbe_x", "pbe_c", "evaluate", "integrate", "density_on_points",
     "grid_and_weights",

@@ -12,7 +12,7 @@ import numpy as np
 
 from .basis import collocation
 from .functionals import evaluate
-from .partition import ssf_weights
+from .partition import becke_weights, ssf_weights
 from .quadrature import molecular_grid
 
 
@@ -26,25 +26,33 @@ def density_on_points(points, coords, basis, P, eta, grad=True):
 
 
 def grid_and_weights(coords, mk_alpha, n_rad, ang, ssf_a=0.64, atom_mask=None,
-                     progress=None, point_slice=None):
+                     progress=None, point_slice=None, partition="ssf", becke_radius=None):
     pts, wq, parent = molecular_grid(coords, mk_alpha, n_rad, ang, atom_mask)
     if point_slice is not None:
         pts, wq, parent = pts[point_slice], wq[point_slice], parent[point_slice]
-    w = ssf_weights(pts, wq, parent, coords, ssf_a, progress=progress)
+    if partition == "becke":
+        w = becke_weights(pts, wq, parent, coords, becke_radius, progress=progress)
+    elif partition == "ssf":
+        w = ssf_weights(pts, wq, parent, coords, ssf_a, progress=progress)
+    else:
+        raise ValueError(f"unknown partition {partition}")
     return pts, w, parent
 
 
 def integrate(coords, mk_alpha, basis, P, functional, n_rad, ang,
               ssf_a=0.64, screen_eta=1e-10, rho_thresh=1e-15, atom_mask=None,
-              chunk=None, details=False, progress=None, point_slice=None):
+              chunk=None, details=False, progress=None, point_slice=None,
+              partition="ssf", becke_radius=None):
     """Return (E_xc, N_e, V_xc) [and per-point details when asked].
     progress(stage, done, total), if given, is called after every chunk;
     point_slice, if given, restricts the sums to that slice of the grid
-    points (a sample of the work)."""
+    points (a sample of the work); partition "ssf" (default) or "becke"
+    (with becke_radius, the atomic radii of the size adjustment, or None)."""
     coords = np.asarray(coords, dtype=np.float64)
     gga = functional == "pbe"
     pts, w, parent = grid_and_weights(coords, mk_alpha, n_rad, ang, ssf_a,
-                                      atom_mask, progress, point_slice)
+                                      atom_mask, progress, point_slice, partition,
+                                      becke_radius)
     nbf = basis.nbf
     if chunk is None:
         chunk = max(256, min(8192, int(2e7 // max(nbf, 1))))

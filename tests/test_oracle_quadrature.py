@@ -16,7 +16,7 @@ def _dfact(n):
     return r
 
 
-@pytest.mark.parametrize("n_ang,degree", [(302, 29), (590, 41)])
+@pytest.mark.parametrize("n_ang,degree", [(302, 29), (590, 41), (974, 53)])
 def test_lebedev_moment_exactness(n_ang, degree):
     """A Lebedev rule of degree L integrates x^a y^b z^c over the sphere
     exactly for a+b+c <= L: 4 pi (a-1)!!(b-1)!!(c-1)!!/(a+b+c+1)!! for even
@@ -37,7 +37,7 @@ def test_lebedev_moment_exactness(n_ang, degree):
 
 
 @pytest.mark.parametrize("n_rad,n_ang,count", [(75, 302, 22650), (99, 590, 58410),
-                                               (100, 590, 59000)])
+                                               (100, 590, 59000), (175, 974, 170450)])
 def test_point_counts(n_rad, n_ang, count):
     """Table 2: N_g^A = N_rad x N_ang (no pruning)."""
     pts, w = oracle.atomic_grid(np.zeros(3), n_rad, 5.0, lebedev_table(n_ang))

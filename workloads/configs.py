@@ -17,6 +17,10 @@ from .molecules import Molecule, water, water_cluster, peptide_chain
 
 # Mura-Knowles radial scale per element (5.0 for H, C, N, O).
 MK_ALPHA = {1: 5.0, 6: 5.0, 7: 5.0, 8: 5.0}
+# Atomic radii for the size adjustment of Becke's partition: Bragg-Slater
+# radii in angstrom (Slater, J. Chem. Phys. 41, 3199 (1964)), with 0.35 for
+# hydrogen as Becke chose; only their ratios matter.
+BECKE_RADIUS = {1: 0.35, 6: 0.70, 7: 0.65, 8: 0.60}
 
 
 @dataclass
@@ -47,6 +51,10 @@ class Workload:
     @property
     def mk_alpha(self):
         return np.array([MK_ALPHA[int(z)] for z in self.mol.Z])
+
+    @property
+    def becke_radius(self):
+        return np.array([BECKE_RADIUS[int(z)] for z in self.mol.Z])
 
     @property
     def natoms(self):

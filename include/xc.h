@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define XC_ABI_VERSION 1
+#define XC_ABI_VERSION 2
 
 /* return codes */
 #define XC_OK               0
@@ -91,13 +91,20 @@ typedef struct xc_molecule {
 } xc_molecule;
 
 /*
- * Contracted Cartesian Gaussian shells (Sec. 2.1, eq. gau_cart). Shell s sits
- * on atom shell_atom[s], has angular momentum shell_L[s] (0..3) and
- * shell_nprim[s] (1..16) primitives; exponents and coefficients are packed
- * in shell order and the coefficients are used as given (no normalisation
- * is applied). A shell holds (L+1)(L+2)/2 functions ordered xx, xy, xz, yy,
- * yz, zz (for L = 2; lexicographic in general); the global function order is
- * shell order. Borrowed for the duration of the call only.
+ * Contracted Gaussian shells (Sec. 2.1, eq. gau_cart). Shell s sits on atom
+ * shell_atom[s], has angular momentum shell_L[s] (0..3) and shell_nprim[s]
+ * (1..16) primitives; exponents and coefficients are packed in shell order
+ * and the coefficients are used as given (no normalisation is applied).
+ * A Cartesian shell holds (L+1)(L+2)/2 functions ordered xx, xy, xz, yy, yz,
+ * zz (for L = 2; lexicographic in general). A spherical shell (shell_pure[s]
+ * = 1 and L >= 2; Sec. 2.1's spherical-harmonic combinations, as in the
+ * cc-pVDZ basis sets of Table 1) holds the 2L+1 real solid harmonics
+ * S_{L,m}(r - R) times the same radial factor, m = -L..L, Racah-normalised
+ * (the integral of S_{L,m}^2 over the unit sphere is 4 pi / (2L+1), that of
+ * x^L): for L = 2, sqrt3 xy, sqrt3 yz, z^2 - (x^2+y^2)/2, sqrt3 xz,
+ * sqrt3/2 (x^2-y^2). Shells with L <= 1 are Cartesian whatever their flag.
+ * shell_pure may be NULL (every shell Cartesian). The global function order
+ * is shell order. Borrowed for the duration of the call only.
  */
 typedef struct xc_basis {
     int nshells;
@@ -106,6 +113,7 @@ typedef struct xc_basis {
     const int* shell_nprim;
     const double* prim_alpha;   /* sum(nprim), > 0 */
     const double* prim_coef;    /* sum(nprim) */
+    const int* shell_pure;      /* nshells flags 0/1, or NULL */
 } xc_basis;
 
 /*
@@ -124,7 +132,20 @@ typedef struct xc_basis {
  *              1: consecutive small sibling cuboids are joined while the
  *              joined count stays <= batch_max (fewer, fuller batches; the
  *              result is the same either way)
+ *  partition   XC_PARTITION_SSF: Stratmann-Scuseria-Frisch (the paper's
+ *              choice, Sec. 2.2); XC_PARTITION_BECKE: Becke's partition (one
+ *              of the choices Sec. 2.2 lists; J. Chem. Phys. 88, 2547 (1988)):
+ *              s(nu) = (1 - p(p(p(nu))))/2 with p(x) = 3x/2 - x^3/2 and
+ *              nu_AB = mu_AB + a_AB (1 - mu_AB^2), P_A = prod_{B != A} s(nu_AB),
+ *              p_A = P_A / sum_B P_B. Becke needs natoms <= 1024
+ *              (XC_ERR_UNSUPPORTED otherwise); ssf_a is then ignored.
+ *  becke_radius NULL (a_AB = 0), or natoms atomic radii for Becke's size
+ *              adjustment: chi = R_A / R_B, u = (chi - 1)/(chi + 1),
+ *              a_AB = u / (u^2 - 1) clipped to [-1/2, 1/2] (only ratios
+ *              matter; > 0). Ignored for SSF.
  */
+#define XC_PARTITION_SSF   0
+#define XC_PARTITION_BECKE 1
 typedef struct xc_grid_spec {
     int n_rad;
     int n_ang;
@@ -135,6 +156,8 @@ typedef struct xc_grid_spec {
     double rho_thresh;
     const unsigned char* atom_mask;
     int batch_merge;
+    int partition;
+    const double* becke_radius;
 } xc_grid_spec;
 
 /*
@@ -349,7 +372,16 @@ int xc_context_destroy(xc_context* ctx);
  *  - every step co-batches the pending grid batches of all in-flight
  *    integrations (round-robin, one batch of each in turn, until the wave
  *    scratch is full) into the same launches, so integrations that arrive
- *    while others run join the next step.
+ *    while others run join the next step;
+ *  - grids are built by a thread of the engine on a stream of its own
+ *    (default priority), so building a new request's grid never holds up
+ *    the steps of the requests already running; a request takes part in
+ *    steps once its grid is built;
+ *  - with cache_phi, an admitted request also keeps its collocation
+ *    matrices Phi^j (Sec. 2.2, Alg. 4; they depend on the grid and the basis
+ *    only) on the device when its footprint with them still fits the
+ *    budget: its first integration writes them, later ones skip the
+ *    collocation (the results are the same bit for bit).
  * Device buffers passed to xc_engine_submit must stay valid until the
  * ticket polls done. Calls on one engine must not overlap.
  */
@@ -359,6 +391,8 @@ typedef struct xc_engine_opts {
     void* stream;        /* hipStream_t for all engine work (NULL: null stream) */
     size_t hbm_budget;   /* device bytes admitted requests may hold; 0: half the free memory */
     size_t wave_bytes;   /* scratch of one co-batched step; 0: min(free/8, 8 GiB) */
+    int cache_phi;       /* 1: keep admitted requests' Phi on the device across their
+                            integrations when the budget allows; 0: recompute it */
 } xc_engine_opts;
 
 typedef struct xc_engine_info {
@@ -371,6 +405,8 @@ typedef struct xc_engine_info {
     long long steps;
     long long batches_launched;
     long long completed;        /* integrations polled done */
+    long long colloc_batches;   /* batches whose collocation ran */
+    int phi_cached;             /* admitted requests keeping their Phi */
 } xc_engine_info;
 
 /* Create an engine; allocates its wave scratch. */
@@ -389,9 +425,12 @@ int xc_engine_submit(xc_engine* eng, long long req_id, const double* d_P,
                      double* d_V, double* d_EN, long long* ticket);
 
 /*
- * Admit waiting requests that fit (builds their grids; synchronises the
- * stream while doing so), then launch one co-batched step. *n_batches (may
- * be NULL) receives the number of batches launched.
+ * Hand waiting requests that fit to the grid builder, finish the admission
+ * of those whose grids are built, then launch one co-batched step.
+ * *n_batches (may be NULL) receives the number of batches launched. A
+ * request whose grid cannot be built (or has a batch larger than the wave
+ * scratch) leaves the queue: the call returns that error, and polls of its
+ * tickets return it too.
  */
 int xc_engine_step(xc_engine* eng, int* n_batches);
 

@@ -30,6 +30,10 @@ XC_MIXED_FP32 = 1
 XC_MIXED_BF16 = 2
 XC_MIXED_FP32_V = 3
 
+XC_PARTITION_SSF = 0
+XC_PARTITION_BECKE = 1
+PARTITIONS = {"ssf": XC_PARTITION_SSF, "becke": XC_PARTITION_BECKE}
+
 FUNCTIONALS = {"lda": XC_LDA_SVWN5, "svwn5": XC_LDA_SVWN5, "pbe": XC_GGA_PBE}
 PRECISIONS = {"fp64": XC_FP64, "fp32": XC_MIXED_FP32, "bf16": XC_MIXED_BF16,
               "fp32v": XC_MIXED_FP32_V}
@@ -43,14 +47,16 @@ class XcMolecule(Structure):
 class XcBasis(Structure):
     _fields_ = [("nshells", c_int), ("shell_atom", POINTER(c_int)),
                 ("shell_L", POINTER(c_int)), ("shell_nprim", POINTER(c_int)),
-                ("prim_alpha", POINTER(c_double)), ("prim_coef", POINTER(c_double))]
+                ("prim_alpha", POINTER(c_double)), ("prim_coef", POINTER(c_double)),
+                ("shell_pure", POINTER(c_int))]
 
 
 class XcGridSpec(Structure):
     _fields_ = [("n_rad", c_int), ("n_ang", c_int), ("ang_xyzw", POINTER(c_double)),
                 ("ssf_a", c_double), ("screen_eta", c_double), ("batch_max", c_int),
                 ("rho_thresh", c_double), ("atom_mask", POINTER(c_ubyte)),
-                ("batch_merge", c_int)]
+                ("batch_merge", c_int), ("partition", c_int),
+                ("becke_radius", POINTER(c_double))]
 
 
 class XcDeviceOpts(Structure):
@@ -82,14 +88,16 @@ class XcTiming(Structure):
 
 
 class XcEngineOpts(Structure):
-    _fields_ = [("stream", c_void_p), ("hbm_budget", c_size_t), ("wave_bytes", c_size_t)]
+    _fields_ = [("stream", c_void_p), ("hbm_budget", c_size_t), ("wave_bytes", c_size_t),
+                ("cache_phi", c_int)]
 
 
 class XcEngineInfo(Structure):
     _fields_ = [("waiting", c_int), ("admitted", c_int), ("in_flight", c_int),
                 ("bytes_used", c_size_t), ("budget", c_size_t), ("wave_bytes", c_size_t),
                 ("steps", c_longlong), ("batches_launched", c_longlong),
-                ("completed", c_longlong)]
+                ("completed", c_longlong), ("colloc_batches", c_longlong),
+                ("phi_cached", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -205,19 +213,28 @@ class _Inputs:
         self.sn = np.ascontiguousarray(basis.shell_nprim, dtype=np.int32)
         self.pa = np.ascontiguousarray(basis.prim_alpha, dtype=np.float64)
         self.pc = np.ascontiguousarray(basis.prim_coef, dtype=np.float64)
+        sp = getattr(basis, "shell_pure", None)
+        self.sp = None if sp is None else np.ascontiguousarray(sp, dtype=np.int32)
         self.ang = np.ascontiguousarray(grid["ang"], dtype=np.float64)
         m = grid.get("atom_mask")
         self.mask = None if m is None else np.ascontiguousarray(m, dtype=np.uint8)
+        br = grid.get("becke_radius")
+        self.brad = None if br is None else np.ascontiguousarray(br, dtype=np.float64)
+        part = grid.get("partition", "ssf")
+        part = PARTITIONS[part] if isinstance(part, str) else int(part)
         self.mol = XcMolecule(self.xyz.shape[0], _dptr(self.xyz), _dptr(self.alpha))
         self.basis = XcBasis(self.sa.shape[0], _iptr(self.sa), _iptr(self.sl),
-                             _iptr(self.sn), _dptr(self.pa), _dptr(self.pc))
+                             _iptr(self.sn), _dptr(self.pa), _dptr(self.pc),
+                             None if self.sp is None else _iptr(self.sp))
         self.grid = XcGridSpec(
             int(grid["n_rad"]), int(grid["n_ang"]), _dptr(self.ang),
             float(grid.get("ssf_a", 0.64)), float(grid.get("screen_eta", 1e-10)),
             int(grid.get("batch_max", 512)), float(grid.get("rho_thresh", 1e-15)),
             None if self.mask is None else self.mask.ctypes.data_as(POINTER(c_ubyte)),
-            int(grid.get("batch_merge", 1)))
-        self.nbf = int(sum((L + 1) * (L + 2) // 2 for L in self.sl))
+            int(grid.get("batch_merge", 1)), part,
+            None if self.brad is None else _dptr(self.brad))
+        self.nbf = int(sum(2 * L + 1 if (self.sp is not None and self.sp[s] and L >= 2)
+                           else (L + 1) * (L + 2) // 2 for s, L in enumerate(self.sl)))
 
 
 def _code(table, v):
@@ -331,9 +348,10 @@ def xc_context_destroy(handle):
     _check(LIB.xc_context_destroy(handle))
 
 
-def xc_engine_create(stream=0, hbm_budget=0, wave_bytes=0):
+def xc_engine_create(stream=0, hbm_budget=0, wave_bytes=0, cache_phi=True):
     h = c_void_p()
-    opts = XcEngineOpts(c_void_p(int(stream)), int(hbm_budget), int(wave_bytes))
+    opts = XcEngineOpts(c_void_p(int(stream)), int(hbm_budget), int(wave_bytes),
+                        1 if cache_phi else 0)
     _check(LIB.xc_engine_create(byref(opts), byref(h)))
     return h
 

@@ -115,7 +115,7 @@ void release_build_temporaries(xc_context* c) {
 
 size_t device_bytes(const xc_context* c) {
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R,
+                            &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->d_becke_a,
                             &c->raw_x, &c->raw_y,
                             &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                             &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
@@ -142,7 +142,11 @@ static void destroy_timer(PhaseTimer& t) {
     t.pool.clear();
 }
 
-static int ncart(int L) { return (L + 1) * (L + 2) / 2; }
+// Functions of shell s of a basis: spherical shells only from L = 2 on.
+static int nfunc(const xc_basis* b, int s) {
+    const int L = b->shell_L[s];
+    return shell_nfunc(L, (b->shell_pure && b->shell_pure[s] && L >= 2) ? 1 : 0);
+}
 
 static bool finite(double v) { return std::isfinite(v); }
 
@@ -176,6 +180,8 @@ static int validate_inputs(const xc_molecule* mol, const xc_basis* basis,
         if (basis->shell_L[s] > kMaxL) return fail(XC_ERR_UNSUPPORTED, "angular momentum above 3");
         if (basis->shell_nprim[s] < 1) return fail(XC_ERR_INVALID_ARG, "shell without primitives");
         if (basis->shell_nprim[s] > kMaxPrim) return fail(XC_ERR_UNSUPPORTED, "more than 16 primitives");
+        if (basis->shell_pure && basis->shell_pure[s] != 0 && basis->shell_pure[s] != 1)
+            return fail(XC_ERR_INVALID_ARG, "shell_pure flags must be 0 or 1");
         np += basis->shell_nprim[s];
     }
     for (long long p = 0; p < np; ++p) {
@@ -189,7 +195,18 @@ static int validate_inputs(const xc_molecule* mol, const xc_basis* basis,
         return fail(XC_ERR_INVALID_ARG, "too many points per atom");
     for (long long k = 0; k < 4LL * g->n_ang; ++k)
         if (!finite(g->ang_xyzw[k])) return fail(XC_ERR_INVALID_ARG, "non-finite angular table");
-    if (!(g->ssf_a > 0.0 && g->ssf_a < 1.0)) return fail(XC_ERR_INVALID_ARG, "ssf_a must lie in (0, 1)");
+    if (g->partition != XC_PARTITION_SSF && g->partition != XC_PARTITION_BECKE)
+        return fail(XC_ERR_INVALID_ARG, "unknown partition");
+    if (g->partition == XC_PARTITION_SSF && !(g->ssf_a > 0.0 && g->ssf_a < 1.0))
+        return fail(XC_ERR_INVALID_ARG, "ssf_a must lie in (0, 1)");
+    if (g->partition == XC_PARTITION_BECKE) {
+        if (mol->natoms > kSsfWaveMaxAtoms)
+            return fail(XC_ERR_UNSUPPORTED, "Becke's partition is limited to 1024 atoms");
+        if (g->becke_radius)
+            for (int a = 0; a < mol->natoms; ++a)
+                if (!(g->becke_radius[a] > 0.0) || !finite(g->becke_radius[a]))
+                    return fail(XC_ERR_INVALID_ARG, "becke_radius must be positive");
+    }
     if (!(g->screen_eta >= 0.0) || !finite(g->screen_eta))
         return fail(XC_ERR_INVALID_ARG, "screen_eta must be >= 0");
     if (g->batch_max < 16 || g->batch_max > kMaxBatch)
@@ -210,7 +227,7 @@ static int check_func_prec(int functional, int precision) {
 
 static void release_all(xc_context* c) {
     DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
-                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R,
+                      &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->d_becke_a,
                       &c->raw_x, &c->raw_y,
                       &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
                       &c->tx, &c->ty, &c->tz, &c->tw, &c->tidx, &c->blk_count,
@@ -273,7 +290,8 @@ static int plan_waves(xc_context* c) {
         const size_t bytes = batch_scratch_bytes(w);
         if (cur.count > 0 && used + bytes > budget) close_wave();
         w.phi_off = (long long)(used / 8);
-        w.part_off = (long long)(used / 8 + kSlabs * slab);
+        w.z_off = w.phi_off + (long long)(batch_phi_bytes(w) / 8);
+        w.part_off = w.z_off + (long long)slab;
         w.pt_off = b.begin;
         w.shell_off = c->h_shoff[j];
         w.func_off = c->h_fnoff[j];
@@ -403,6 +421,10 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
         c->shell_atom.push_back(a);
         c->shell_L.push_back(basis->shell_L[s]);
         c->shell_nprim.push_back(basis->shell_nprim[s]);
+        const int pure = (basis->shell_pure && basis->shell_pure[s] && basis->shell_L[s] >= 2)
+                             ? 1 : 0;
+        c->shell_pure.push_back(pure);
+        c->any_pure = c->any_pure || pure;
         c->prim_off.push_back(po);
         c->first_func.push_back(ff);
         sh[s].x = c->atoms4[4 * a];
@@ -413,19 +435,24 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
         sh[s].nprim = basis->shell_nprim[s];
         sh[s].prim_off = po;
         sh[s].first_func = ff;
+        sh[s].pure = pure;
+        sh[s].pad_ = 0;
         po += basis->shell_nprim[s];
-        ff += ncart(basis->shell_L[s]);
+        ff += nfunc(basis, s);
     }
     c->nbf = ff;
     std::vector<int> fshell;
     for (int s2 = 0; s2 < c->nshells; ++s2)
-        for (int k = 0; k < ncart(basis->shell_L[s2]); ++k) fshell.push_back(s2);
+        for (int k = 0; k < nfunc(basis, s2); ++k) fshell.push_back(s2);
     c->prim_alpha.assign(basis->prim_alpha, basis->prim_alpha + po);
     c->prim_coef.assign(basis->prim_coef, basis->prim_coef + po);
     c->n_rad = g->n_rad;
     c->n_ang = g->n_ang;
     c->ang.assign(g->ang_xyzw, g->ang_xyzw + 4 * (size_t)g->n_ang);
-    c->ssf_a = g->ssf_a;
+    c->ssf_a = g->partition == XC_PARTITION_SSF ? g->ssf_a : 0.64;
+    c->partition = g->partition;
+    if (g->partition == XC_PARTITION_BECKE && g->becke_radius)
+        c->becke_radius.assign(g->becke_radius, g->becke_radius + c->natoms);
     c->screen_eta = g->screen_eta;
     c->rho_thresh = g->rho_thresh;
     c->batch_max = g->batch_max;
@@ -438,6 +465,8 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
     if (rc == XC_OK) rc = upload(c->d_atoms, c->atoms4.data(), 8 * c->atoms4.size(), c->stream);
     if (rc == XC_OK) rc = dev_reserve(c->d_invR, 8 * (size_t)c->natoms * c->natoms);
     if (rc == XC_OK) rc = dev_reserve(c->d_nnhalf, 8 * (size_t)c->natoms);
+    if (rc == XC_OK && c->partition == XC_PARTITION_BECKE)
+        rc = dev_reserve(c->d_becke_a, 8 * (size_t)c->natoms * c->natoms);
     if (rc == XC_OK && c->natoms > kSsfWaveMaxAtoms && c->natoms <= kNbrMaxAtoms) {
         rc = dev_reserve(c->d_nbr_idx, sizeof(int) * (size_t)c->natoms * c->natoms);
         if (rc == XC_OK) rc = dev_reserve(c->d_nbr_R, 8 * (size_t)c->natoms * c->natoms);
@@ -511,7 +540,7 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
     size_t pers = 0;
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells,
                             &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
-                            &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
+                            &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->d_becke_a, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->epart,
                             &c->npart, &c->d_req};
@@ -530,7 +559,7 @@ int xc_context_footprint(xc_context* c, size_t* min_bytes, size_t* cached_bytes)
         // map, per-wave tile-count prefixes)
         const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells,
                                 &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
-                                &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->px, &c->py,
+                                &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->d_becke_a, &c->px, &c->py,
                                 &c->pz, &c->pw, &c->pidx, &c->batches, &c->shell_list,
                                 &c->shell_loff, &c->func_list, &c->d_wb, &c->epart,
                                 &c->npart, &c->d_req};
@@ -661,7 +690,7 @@ int xc_integrate(const xc_molecule* mol, const xc_basis* basis, const xc_grid_sp
     XC_TRY(check_func_prec(functional, precision));
     if (!P || !V || !E_xc || !N_e) return fail(XC_ERR_INVALID_ARG, "null P, V, E_xc or N_e");
     int want = 0;
-    for (int s = 0; s < basis->nshells; ++s) want += ncart(basis->shell_L[s]);
+    for (int s = 0; s < basis->nshells; ++s) want += nfunc(basis, s);
     if (nbf != want) return fail(XC_ERR_INVALID_ARG, "nbf does not match the basis");
     xc_context* c = nullptr;
     XC_TRY(xc_context_create(mol, basis, g, nullptr, &c));

@@ -373,7 +373,7 @@ __global__ void k_screen_count(const Cell* batches, const ShellDev* shells,
         const ShellDev sh = shells[s];
         if (shell_meets_box(sh, b)) {
             cs += 1;
-            cf += ncart(sh.L);
+            cf += shell_nfunc(sh.L, sh.pure);
         }
     }
     __shared__ int r1[256], r2[256];
@@ -409,7 +409,7 @@ __global__ void k_screen_fill(const Cell* batches, const ShellDev* shells, int n
         if (s < nshells) {
             sh = shells[s];
             keep = shell_meets_box(sh, b);
-            nf = keep ? ncart(sh.L) : 0;
+            nf = keep ? shell_nfunc(sh.L, sh.pure) : 0;
         }
         int ts, tf;
         const int ps = block_exclusive_scan(keep, smem, ts);

@@ -78,6 +78,22 @@ __global__ void k_atom_neighbours(const double4* atoms, int natoms, int* nbr_idx
     }
 }
 
+// Becke's size adjustment a_AB from the atomic radii (one thread per pair):
+// chi = R_A / R_B, u = (chi - 1)/(chi + 1), a = u / (u^2 - 1), clipped to
+// [-1/2, 1/2]; zero on the diagonal and without radii.
+__global__ void k_becke_adjust(const double* radius, int natoms, double* adj) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long long)natoms * natoms) return;
+    const int A = (int)(k / natoms), B = (int)(k - (long long)A * natoms);
+    double a = 0.0;
+    if (radius && A != B) {
+        const double chi = radius[A] / radius[B];
+        const double u = (chi - 1.0) / (chi + 1.0);
+        a = fmin(fmax(u / (u * u - 1.0), -0.5), 0.5);
+    }
+    adj[k] = a;
+}
+
 int launch_shell_setup(xc_context* c) {
     hipLaunchKernelGGL(k_shell_rcut, dim3(grid_1d(c->nshells, 128)), dim3(128), 0,
                        c->stream, (ShellDev*)c->d_shells.p, c->nshells,
@@ -87,6 +103,22 @@ int launch_shell_setup(xc_context* c) {
                        c->stream, (const double4*)c->d_atoms.p, c->natoms, c->ssf_a,
                        (double*)c->d_invR.p, (double*)c->d_nnhalf.p);
     XC_HIP(hipGetLastError());
+    if (c->partition == XC_PARTITION_BECKE) {
+        const double* rad = nullptr;
+        DevBuf tmp;
+        if (!c->becke_radius.empty()) {
+            XC_TRY(upload(tmp, c->becke_radius.data(), 8 * c->becke_radius.size(), c->stream));
+            rad = (const double*)tmp.p;
+        }
+        const long long np = (long long)c->natoms * c->natoms;
+        hipLaunchKernelGGL(k_becke_adjust, dim3(grid_1d(np, 256)), dim3(256), 0, c->stream,
+                           rad, c->natoms, (double*)c->d_becke_a.p);
+        XC_HIP(hipGetLastError());
+        if (tmp.p) {
+            XC_HIP(hipStreamSynchronize(c->stream));
+            dev_release(tmp);
+        }
+    }
     if (c->natoms > kSsfWaveMaxAtoms && c->natoms <= kNbrMaxAtoms) {
         hipLaunchKernelGGL(k_atom_neighbours, dim3(c->natoms), dim3(256),
                            sizeof(double) * (size_t)c->natoms, c->stream,
@@ -446,9 +478,97 @@ __global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const in
     }
 }
 
+// ------------------------------------------ Becke partition, one wave a point --
+// Becke's cell function s(nu) = (1 - p(p(p(nu))))/2, p(x) = 3x/2 - x^3/2.
+__device__ inline double becke_s(double nu) {
+    double f = nu;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f = f * (1.5 - 0.5 * f * f);
+    return 0.5 * (1.0 - f);
+}
+
+// Weights with Becke's partition (molecules up to kSsfWaveMaxAtoms atoms).
+// No factor is exactly 0 or 1 away from the nuclei, so every point needs
+// every atom's cell product: the wave takes the points of its lanes one at a
+// time, lane l holds atoms l, l + 64, ... (their distances to the point), and
+// each P_C = prod_{B != C} s(nu_CB), nu_CB = mu_CB + a_CB (1 - mu_CB^2), is
+// spread over the lanes and finished by a butterfly. Points of zero weight
+// are skipped.
+template <int NPER>
+__global__ __launch_bounds__(256) void k_becke_wave(long long n, int npa, const int* gatoms,
+                                                    const double4* atoms_g,
+                                                    const double* invR, const double* adj,
+                                                    int natoms, const double* X,
+                                                    const double* Y, const double* Z,
+                                                    double* W) {
+    extern __shared__ double4 sat[];
+    for (int k = threadIdx.x; k < natoms; k += blockDim.x) sat[k] = atoms_g[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double x = 0.0, y = 0.0, z = 0.0, w = 0.0;
+    int A = 0;
+    bool need = false;
+    if (i < n && natoms > 1) {
+        w = W[i];
+        if (w != 0.0) {
+            A = gatoms[(int)(i / npa)];
+            x = X[i];
+            y = Y[i];
+            z = Z[i];
+            need = true;
+        }
+    }
+    unsigned long long todo = __ballot(need);
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const double px = readlane_f64(x, l), py = readlane_f64(y, l), pz = readlane_f64(z, l);
+        const int pA = __builtin_amdgcn_readlane(A, l);
+        double d[NPER];
+#pragma unroll
+        for (int j = 0; j < NPER; ++j) {
+            const int B = lane + 64 * j;
+            d[j] = B < natoms ? sqrt(dist2_to(sat[B], px, py, pz)) : 0.0;
+        }
+        double sum = 0.0, PA = 0.0;
+        for (int C = 0; C < natoms; ++C) {
+            const double dC = sqrt(dist2_to(sat[C], px, py, pz));
+            const double* ir = invR + (size_t)C * natoms;
+            const double* ar = adj + (size_t)C * natoms;
+            double p = 1.0;
+#pragma unroll
+            for (int j = 0; j < NPER; ++j) {
+                const int B = lane + 64 * j;
+                if (B < natoms && B != C) {
+                    const double mu = (dC - d[j]) * ir[B];
+                    p *= becke_s(mu + ar[B] * (1.0 - mu * mu));
+                }
+            }
+            const double PC = wave_product(p);
+            sum += PC;
+            if (C == pA) PA = PC;
+        }
+        if (lane == l) W[i] = w * (PA / sum);
+    }
+}
+
 int launch_ssf(xc_context* c) {
     PhaseScope ps(c, XC_PHASE_WEIGHTS);
     const int npa = c->n_rad * c->n_ang;
+    if (c->partition == XC_PARTITION_BECKE) {
+        const int nper = (c->natoms + 63) / 64;
+        auto k = nper <= 1 ? k_becke_wave<1> : nper <= 2 ? k_becke_wave<2>
+               : nper <= 4 ? k_becke_wave<4> : nper <= 8 ? k_becke_wave<8> : k_becke_wave<16>;
+        hipLaunchKernelGGL(k, dim3(grid_1d(c->n_nominal, 256)), dim3(256),
+                           sizeof(double4) * (size_t)c->natoms, c->stream, c->n_nominal, npa,
+                           (const int*)c->d_gatoms.p, (const double4*)c->d_atoms.p,
+                           (const double*)c->d_invR.p, (const double*)c->d_becke_a.p,
+                           c->natoms, (const double*)c->raw_x.p, (const double*)c->raw_y.p,
+                           (const double*)c->raw_z.p, (double*)c->raw_w.p);
+        XC_HIP(hipGetLastError());
+        return XC_OK;
+    }
     if (c->natoms <= kSsfWaveMaxAtoms) {
         const int nper = (c->natoms + 63) / 64;
         auto k = nper <= 1 ? k_ssf_wave<1> : nper <= 2 ? k_ssf_wave<2>

@@ -61,9 +61,15 @@ struct ReqG {
     gptr<double> V, epart, npart;
     gptr<const unsigned long long> Pdig;
     gptr<const double> Pscale;
+    char* phi_base;
     double rho_thresh;
     int nbf;
 };
+
+// Start of a batch's Phi slab: the request's Phi store, or the wave scratch.
+__device__ inline char* phi_slab(const WaveBatch& B, const ReqG& R, char* scratch) {
+    return (R.phi_base ? R.phi_base : scratch) + 8 * B.phi_off;
+}
 
 __device__ inline ReqG global_view(const ReqDev& r) {
     ReqG g;
@@ -84,6 +90,7 @@ __device__ inline ReqG global_view(const ReqDev& r) {
     g.npart = to_global(r.npart);
     g.Pdig = to_global(r.Pdig);
     g.Pscale = to_global(r.Pscale);
+    g.phi_base = r.phi_base;
     g.rho_thresh = r.rho_thresh;
     g.nbf = r.nbf;
     return g;
@@ -99,7 +106,61 @@ __device__ inline ShellDev load_shell(gptr<const ShellDev> p) {
     s.nprim = p->nprim;
     s.prim_off = p->prim_off;
     s.first_func = p->first_func;
+    s.pure = p->pure;
     return s;
+}
+
+// Digits of a value y with |y| <= 1 for the split-BF16 density contraction:
+// d0 = rint(128 y), then d_u = rint(256 r) with r the remainder scaled by
+// the previous step; every digit is an integer of magnitude <= 128 (exact in
+// BF16), every subtraction is exact (its operands lie within a factor of
+// two, or the digit is zero), and y = sum_u d_u 2^{-7-8u} up to a remainder
+// below 2^{-32}. Packed as four BF16 bit patterns, digit u in bits
+// 16 u .. 16 u + 15.
+__device__ inline unsigned long long digits_packed(double y) {
+    double a = y * 128.0;
+    double q = rint(a);
+    unsigned long long w = __builtin_bit_cast(unsigned short, (__bf16)(float)q);
+#pragma unroll
+    for (int u = 1; u < 4; ++u) {
+        a = (a - q) * 256.0;
+        q = rint(a);
+        w |= (unsigned long long)__builtin_bit_cast(unsigned short, (__bf16)(float)q)
+             << (16 * u);
+    }
+    return w;
+}
+
+// Real solid harmonics of a spherical shell (Racah normalisation, m = -L..L)
+// as combinations of its Cartesian components in lexicographic order:
+// S_m = sum_c sph<L>(m, c) x^l y^m z^n.
+//  L = 2 (xx xy xz yy yz zz): sqrt3 xy, sqrt3 yz, z^2 - (x^2 + y^2)/2,
+//        sqrt3 xz, sqrt3/2 (x^2 - y^2)
+//  L = 3 (xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz):
+//        sqrt10/4 (3 x^2 y - y^3), sqrt15 xyz, sqrt6/4 y (4 z^2 - x^2 - y^2),
+//        z (2 z^2 - 3 x^2 - 3 y^2)/2, sqrt6/4 x (4 z^2 - x^2 - y^2),
+//        sqrt15/2 z (x^2 - y^2), sqrt10/4 (x^3 - 3 x y^2)
+constexpr double kSqrt3 = 1.7320508075688772;
+constexpr double kSqrt15 = 3.8729833462074170;
+constexpr double kSqrt6q = 0.61237243569579452;   // sqrt6 / 4
+constexpr double kSqrt10q = 0.79056941504209483;  // sqrt10 / 4
+constexpr double kSph2[5][6] = {{0, kSqrt3, 0, 0, 0, 0},
+                                {0, 0, 0, 0, kSqrt3, 0},
+                                {-0.5, 0, 0, -0.5, 0, 1.0},
+                                {0, 0, kSqrt3, 0, 0, 0},
+                                {0.5 * kSqrt3, 0, 0, -0.5 * kSqrt3, 0, 0}};
+constexpr double kSph3[7][10] = {
+    {0, 3 * kSqrt10q, 0, 0, 0, 0, -kSqrt10q, 0, 0, 0},
+    {0, 0, 0, 0, kSqrt15, 0, 0, 0, 0, 0},
+    {0, -kSqrt6q, 0, 0, 0, 0, -kSqrt6q, 0, 4 * kSqrt6q, 0},
+    {0, 0, -1.5, 0, 0, 0, 0, -1.5, 0, 1.0},
+    {-kSqrt6q, 0, 0, -kSqrt6q, 0, 4 * kSqrt6q, 0, 0, 0, 0},
+    {0, 0, 0.5 * kSqrt15, 0, 0, 0, 0, -0.5 * kSqrt15, 0, 0},
+    {kSqrt10q, 0, 0, -3 * kSqrt10q, 0, 0, 0, 0, 0, 0}};
+template <int L>
+__device__ constexpr double sph(int m, int c) {
+    if constexpr (L == 2) return kSph2[m][c];
+    else return kSph3[m][c];
 }
 
 // ------------------------------------------------------------ collocation --
@@ -172,7 +233,9 @@ __device__ inline double dist2_nc(double x, double y, double z, const ShellDev& 
 // z = A (a rad + drad b.d) + rad b.grad A, so the shell-wide factors are
 // formed once and each component costs a few products with its exponents
 // known at compile time.
-template <int L, typename T>
+// PURE: the Cartesian z values are formed in registers and combined into
+// the shell's 2L+1 spherical rows.
+template <int L, typename T, bool PURE = false>
 __device__ inline void z_shell(double dx, double dy, double dz, double rad, double drad,
                                double a, double bx, double by, double bz, T* out,
                                int ngp) {
@@ -186,6 +249,7 @@ __device__ inline void z_shell(double dx, double dy, double dz, double rad, doub
     }
     const double t0 = a * rad + (bx * dx + by * dy + bz * dz) * drad;
     const double rbx = rad * bx, rby = rad * by, rbz = rad * bz;
+    double zc[PURE ? (L + 1) * (L + 2) / 2 : 1];
     int c = 0;
 #pragma unroll
     for (int l = L; l >= 0; --l) {
@@ -197,8 +261,19 @@ __device__ inline void z_shell(double dx, double dy, double dz, double rad, doub
             if (l > 0) z += rbx * (l * xp[l - 1] * yz);
             if (m > 0) z += rby * (m * xp[l] * yp[m - 1] * zp[n]);
             if (n > 0) z += rbz * (n * xp[l] * yp[m] * zp[n - 1]);
-            out[(size_t)c * ngp] = T(z);
+            if constexpr (PURE) zc[c] = z;
+            else out[(size_t)c * ngp] = T(z);
             ++c;
+        }
+    }
+    if constexpr (PURE) {
+#pragma unroll
+        for (int m = 0; m < 2 * L + 1; ++m) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < (L + 1) * (L + 2) / 2; ++k)
+                if (sph<L>(m, k) != 0.0) v = fma(sph<L>(m, k), zc[k], v);
+            out[(size_t)m * ngp] = T(v);
         }
     }
 }
@@ -231,20 +306,59 @@ __device__ inline double phi_shell(double dx, double dy, double dz, double rad, 
     return mx;
 }
 
+// phi of the 2L+1 spherical functions of a shell (L = 2, 3) at one point:
+// the Cartesian components are formed in registers and combined; returns
+// the largest magnitude written.
+template <int L, typename T>
+__device__ inline double phi_shell_sph(double dx, double dy, double dz, double rad, T* out,
+                                       int ngp) {
+    constexpr int NC = (L + 1) * (L + 2) / 2;
+    double xp[L + 1], yp[L + 1], zp[L + 1];
+    xp[0] = yp[0] = zp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        xp[k] = xp[k - 1] * dx;
+        yp[k] = yp[k - 1] * dy;
+        zp[k] = zp[k - 1] * dz;
+    }
+    double v[NC];
+    int c = 0;
+#pragma unroll
+    for (int l = L; l >= 0; --l)
+#pragma unroll
+        for (int m = L - l; m >= 0; --m) v[c++] = xp[l] * yp[m] * zp[L - l - m];
+    double mx = 0.0;
+#pragma unroll
+    for (int m = 0; m < 2 * L + 1; ++m) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            if (sph<L>(m, k) != 0.0) a = fma(sph<L>(m, k), v[k], a);
+        a *= rad;
+        mx = fmax(mx, fabs(a));
+        out[(size_t)m * ngp] = T(a);
+    }
+    return mx;
+}
+
 // One workgroup per batch; wave w evaluates shells w, w+4, ... of the
 // batch's screened list, one lane per point, so a wave never diverges on
 // the contraction length. Points of the batch are staged in LDS. Values are
 // formed in FP64 in every mode and rounded once on store. SCALE (split-BF16
-// mode): also the digit scale of every point, the least power of two not
-// below max_mu |phi_mu(r_i)| over the batch's functions (1 where all are
-// zero), kept as a running maximum in LDS (the bit patterns of non-negative
-// doubles order like unsigned integers) and written to the batch's scale row.
+// mode): the FP64 values go to the Z slab (free until the Z kernel) while
+// the digit scale of every point, the least power of two not below
+// max_mu |phi_mu(r_i)| over the batch's functions (1 where all are zero), is
+// kept as a running maximum in LDS (the bit patterns of non-negative doubles
+// order like unsigned integers); after a barrier the scales go to the
+// batch's scale row and every value is cut into its four digits
+// (digits_packed), which fill the Phi slab.
 template <typename T, bool SCALE>
 __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb,
                                                 const ReqDev* __restrict__ reqs,
                                                 char* __restrict__ scratch) {
-    exp_table_init();
     const WaveBatch B = wb[blockIdx.x];
+    if (B.flags & kSkipColloc) return;   // Phi already in the request's store
+    exp_table_init();
     const ReqG R = global_view(reqs[B.req]);
     __shared__ double sx[kMaxBatch], sy[kMaxBatch], sz[kMaxBatch];
     __shared__ unsigned long long smax[SCALE ? kMaxBatch : 1];
@@ -256,7 +370,8 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
         if (SCALE) smax[i] = 0ull;
     }
     __syncthreads();
-    T* Phi = (T*)(scratch + 8 * B.phi_off);
+    char* phi = phi_slab(B, R, scratch);
+    T* Phi = SCALE ? (T*)(scratch + 8 * B.z_off) : (T*)phi;
     // zero the padding rows n_b .. n_bp - 1
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) Phi[(size_t)B.nb * B.ngp + k] = T(0);
@@ -273,25 +388,40 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
             else rad = drad = 0.0;
             T* out = Phi + (size_t)loff * B.ngp + i;
             double mx;
-            switch (sh.L) {
-                case 0: mx = phi_shell<0, T>(dx, dy, dz, rad, out, B.ngp); break;
-                case 1: mx = phi_shell<1, T>(dx, dy, dz, rad, out, B.ngp); break;
-                case 2: mx = phi_shell<2, T>(dx, dy, dz, rad, out, B.ngp); break;
-                default: mx = phi_shell<3, T>(dx, dy, dz, rad, out, B.ngp); break;
+            if (sh.pure) {
+                if (sh.L == 2) mx = phi_shell_sph<2, T>(dx, dy, dz, rad, out, B.ngp);
+                else mx = phi_shell_sph<3, T>(dx, dy, dz, rad, out, B.ngp);
+            } else {
+                switch (sh.L) {
+                    case 0: mx = phi_shell<0, T>(dx, dy, dz, rad, out, B.ngp); break;
+                    case 1: mx = phi_shell<1, T>(dx, dy, dz, rad, out, B.ngp); break;
+                    case 2: mx = phi_shell<2, T>(dx, dy, dz, rad, out, B.ngp); break;
+                    default: mx = phi_shell<3, T>(dx, dy, dz, rad, out, B.ngp); break;
+                }
             }
             if (SCALE && mx > 0.0)
                 atomicMax(&smax[i], (unsigned long long)__double_as_longlong(mx));
         }
     }
-    if (SCALE) {
+    if constexpr (SCALE) {
         __syncthreads();
-        double* sc = (double*)(scratch + 8 * B.part_off) + scale_row_off(B);
+        double* sc = (double*)phi + scale_row_off(B);
         for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
             const double m = __longlong_as_double((long long)smax[i]);
             int e = 0;
             (void)frexp(m, &e);  // m = f 2^e with f in [0.5, 1), so m <= 2^e
-            sc[i] = m > 0.0 ? ldexp(1.0, max(e, -1000)) : 1.0;  // 1 / sc stays finite
+            e = max(e, -1000);   // 1 / scale stays finite
+            sc[i] = m > 0.0 ? ldexp(1.0, e) : 1.0;
+            sx[i] = m > 0.0 ? ldexp(1.0, -e) : 1.0;   // the exact inverse, for the cut
         }
+        __syncthreads();
+        const double* val = (const double*)Phi;
+        unsigned long long* dig = (unsigned long long*)phi;
+        for (int r = 0; r < B.nbp; ++r)
+            for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
+                const size_t k = (size_t)r * B.ngp + i;
+                dig[k] = digits_packed(val[k] * sx[i]);
+            }
     }
 }
 
@@ -323,17 +453,34 @@ __device__ inline void shell_radial_wave(const ShellDev& sh, gptr<const double> 
 // GGA, grad phi*X. With phi = A(d) rad and grad phi = grad A rad + A drad d,
 // the sums over the components need only S = sum X A and the three sums
 // X dA/dx, X dA/dy, X dA/dz, formed with the exponents known at compile
-// time. The X values are read first, all at once.
-template <int L, bool GGA>
+// time. The X values are read first, all at once. PURE: the shell's rows
+// are its 2L+1 spherical functions, whose X values are first folded into
+// weights of the Cartesian components (sum_m X_m S_m = sum_c w_c A_c).
+template <int L, bool GGA, bool PURE>
 __device__ inline void rho_shell(int k0, int cnt, double dx, double dy, double dz, double rad,
                                  double drad, const double (*Xs)[kTile + 1], int rl, int c,
                                  double (&q)[4]) {
     constexpr int NC = (L + 1) * (L + 2) / 2;
-    double xv[NC];
+    constexpr int NF = PURE ? 2 * L + 1 : NC;
+    double xv[NF];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
+    for (int k = 0; k < NF; ++k) {
         const double v = Xs[min(max(rl + k - k0, 0), kTile - 1)][c];
         xv[k] = (k >= k0 && k < k0 + cnt) ? v : 0.0;
+    }
+    double wv[NC];
+    if constexpr (PURE) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            double a = 0.0;
+#pragma unroll
+            for (int m = 0; m < NF; ++m)
+                if (sph<L>(m, k) != 0.0) a = fma(sph<L>(m, k), xv[m], a);
+            wv[k] = a;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) wv[k] = xv[k];
     }
     double xp[L + 1], yp[L + 1], zp[L + 1];
     xp[0] = yp[0] = zp[0] = 1.0;
@@ -350,13 +497,13 @@ __device__ inline void rho_shell(int k0, int cnt, double dx, double dy, double d
 #pragma unroll
         for (int m = L - l; m >= 0; --m) {
             const int n = L - l - m;
-            if (comp >= k0 && comp < k0 + cnt) {
+            if (PURE || (comp >= k0 && comp < k0 + cnt)) {
                 const double yz = yp[m] * zp[n];
-                s0 += xv[comp] * (xp[l] * yz);
+                s0 += wv[comp] * (xp[l] * yz);
                 if (GGA) {
-                    if (l > 0) sx += xv[comp] * (l * xp[l - 1] * yz);
-                    if (m > 0) sy += xv[comp] * (m * xp[l] * yp[m - 1] * zp[n]);
-                    if (n > 0) sz += xv[comp] * (n * xp[l] * yp[m] * zp[n - 1]);
+                    if (l > 0) sx += wv[comp] * (l * xp[l - 1] * yz);
+                    if (m > 0) sy += wv[comp] * (m * xp[l] * yp[m - 1] * zp[n]);
+                    if (n > 0) sz += wv[comp] * (n * xp[l] * yp[m] * zp[n - 1]);
                 }
             }
             ++comp;
@@ -392,18 +539,23 @@ __device__ inline void rho_epilogue(const WaveBatch& B, const ReqG& R, int m0, i
     for (int rl = g * 16; rl < rend;) {
         const int sidx = __builtin_amdgcn_readfirstlane(fsh[rl]);
         const ShellDev sh = load_shell(R.shells + sidx);
-        const int nc = ncart(sh.L);
+        const int nc = shell_nfunc(sh.L, sh.pure);
         const int k0 = min(max(__builtin_amdgcn_readfirstlane(frow[rl]) - sh.first_func, 0),
                            nc - 1);
         const int cnt = min(nc - k0, rend - rl);
         double dx, dy, dz, rad, drad;
         const double r2 = dist2_nc(x, y, z, sh, dx, dy, dz);
         shell_radial_wave(sh, R.palpha, R.pcoef, r2, has, rad, drad);
-        switch (sh.L) {
-            case 0: rho_shell<0, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
-            case 1: rho_shell<1, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
-            case 2: rho_shell<2, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
-            default: rho_shell<3, GGA>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+        if (sh.pure) {
+            if (sh.L == 2) rho_shell<2, GGA, true>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q);
+            else rho_shell<3, GGA, true>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q);
+        } else {
+            switch (sh.L) {
+                case 0: rho_shell<0, GGA, false>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+                case 1: rho_shell<1, GGA, false>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+                case 2: rho_shell<2, GGA, false>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+                default: rho_shell<3, GGA, false>(k0, cnt, dx, dy, dz, rad, drad, Xs, rl, c, q); break;
+            }
         }
         rl += cnt;
     }
@@ -448,7 +600,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
     exp_table_init();
-    const T* Phi = (const T*)(scratch + 8 * B.phi_off);
+    const T* Phi = (const T*)phi_slab(B, R, scratch);
     const gptr<const int> fl = func_list + B.func_off;
     // the epilogue's point (one per lane), loaded now so that its latency hides
     const bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
@@ -695,7 +847,7 @@ __global__ __launch_bounds__(256) void k_func(const WaveBatch* __restrict__ wb,
 // lane takes a point (its coordinates and Z factors read once), the wave
 // takes shells wave, wave + 4, ... of the batch's list. No LDS and few
 // registers, so many workgroups share a CU.
-template <typename T>
+template <typename T, bool SPH>
 __global__ __launch_bounds__(256) void k_z(const WaveBatch* __restrict__ wb,
                                            const ReqDev* __restrict__ reqs,
                                            char* __restrict__ scratch) {
@@ -703,7 +855,7 @@ __global__ __launch_bounds__(256) void k_z(const WaveBatch* __restrict__ wb,
     const WaveBatch B = wb[blockIdx.x];
     const ReqG R = global_view(reqs[B.req]);
     const double* fac = (const double*)(scratch + 8 * B.part_off);
-    T* Zm = (T*)(scratch + 8 * (B.phi_off + (long long)B.nbp * B.ngp));
+    T* Zm = (T*)(scratch + 8 * B.z_off);
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     for (long long k = threadIdx.x; k < npad; k += blockDim.x) Zm[(size_t)B.nb * B.ngp + k] = T(0);
     __syncthreads();  // the exponential table
@@ -729,11 +881,16 @@ __global__ __launch_bounds__(256) void k_z(const WaveBatch* __restrict__ wb,
                 shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
             }
             T* out = Zm + (size_t)loff * B.ngp + i;
-            switch (sh.L) {
-                case 0: z_shell<0, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
-                case 1: z_shell<1, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
-                case 2: z_shell<2, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
-                default: z_shell<3, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+            if (SPH && sh.pure) {
+                if (sh.L == 2) z_shell<2, T, SPH>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp);
+                else z_shell<3, T, SPH>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp);
+            } else {
+                switch (sh.L) {
+                    case 0: z_shell<0, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+                    case 1: z_shell<1, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+                    case 2: z_shell<2, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+                    default: z_shell<3, T>(dx, dy, dz, rad, drad, a, bx, by, bz, out, B.ngp); break;
+                }
             }
         }
     }
@@ -763,9 +920,8 @@ __global__ __launch_bounds__(256) void k_syr2k(
     while ((I + 1) * (I + 2) / 2 <= lt) ++I;
     while (I * (I + 1) / 2 > lt) --I;
     const int J = lt - I * (I + 1) / 2;
-    const size_t slab = (size_t)B.nbp * B.ngp;
-    const TP* Phi = (const TP*)(scratch + 8 * B.phi_off);
-    const T* Zm = (const T*)(scratch + 8 * (B.phi_off + (long long)slab));
+    const TP* Phi = (const TP*)phi_slab(B, R, (char*)scratch);
+    const T* Zm = (const T*)(scratch + 8 * B.z_off);
     const gptr<const int> fl = func_list + B.func_off;
 
     // K steps of 8. FP64: one LDS buffer (the next step's operands wait in
@@ -973,34 +1129,15 @@ __device__ inline v4f mfma_bf16x3(const bf16x8& ah, const bf16x8& al, const bf16
     return c;
 }
 
-// Density contraction: exact digit products. A value y with |y| <= 1 (an
-// entry of P over its row's scale, or of Phi over its point's scale, both
-// powers of two) is cut into four digits d0 = rint(128 y), then
-// d_u = rint(256 r) with r the remainder scaled by the previous step; every
-// digit is an integer of magnitude <= 128 (exact in BF16), every subtraction
-// is exact (its operands lie within a factor of two, or the digit is zero),
-// and y = sum_u d_u 2^{-7-8u} up to a remainder below 2^{-32}. A product of
-// two digits is an integer below 2^14 in magnitude and a sum of 2^10 of them
-// stays below 2^24, so FP32 accumulation of digit products is exact however
-// the hardware orders it. The products of digit orders u + v = g (g <= 3,
-// ten products per pair of entries) share one accumulator of weight
-// 2^{-14-8g}; every four K steps (128 terms, at most 4 x 128 products of
-// 2^14, below 2^24) the accumulators are added into FP64 and cleared.
-__device__ inline void digits4(double y, __bf16 (&d)[4]) {
-    double a = y * 128.0;
-    double q = rint(a);
-    d[0] = (__bf16)(float)q;
-#pragma unroll
-    for (int u = 1; u < 4; ++u) {
-        a = (a - q) * 256.0;
-        q = rint(a);
-        d[u] = (__bf16)(float)q;
-    }
-}
-
-__device__ inline unsigned short bf16_bits(__bf16 v) {
-    return __builtin_bit_cast(unsigned short, v);
-}
+// Density contraction: exact digit products. The entries of P over their
+// row's scale and of Phi over their point's scale (both powers of two) are
+// cut into four digits each (digits_packed). A product of two digits is an
+// integer below 2^14 in magnitude and a sum of 2^10 of them stays below
+// 2^24, so FP32 accumulation of digit products is exact however the
+// hardware orders it. The products of digit orders u + v = g (g <= 3, ten
+// products per pair of entries) share one accumulator of weight
+// 2^{-14-8g}; every eight K steps (256 terms: at most 4 x 256 products of
+// 2^14, i.e. 2^24) the accumulators are added into FP64 and cleared.
 __device__ inline __bf16 bits_bf16(unsigned short v) {
     return __builtin_bit_cast(__bf16, v);
 }
@@ -1031,23 +1168,15 @@ __global__ __launch_bounds__(256) void k_p_digits(const double* __restrict__ P, 
     const double inv = mx > 0.0 ? ldexp(1.0, -e) : 1.0;
     if (threadIdx.x == 0) scale[mu] = sc;
     unsigned long long* drow = dig + (size_t)mu * nbf;
-    for (int nu = threadIdx.x; nu < nbf; nu += blockDim.x) {
-        __bf16 d[4];
-        digits4(row[nu] * inv, d);
-        unsigned long long w = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) w |= (unsigned long long)bf16_bits(d[u]) << (16 * u);
-        drow[nu] = w;
-    }
+    for (int nu = threadIdx.x; nu < nbf; nu += blockDim.x) drow[nu] = digits_packed(row[nu] * inv);
 }
 
 // X = P^j Phi^j from digits: X[mu][i] = s_mu s_i 2^{-14}
 // sum_{u+v<=3} 2^{-8(u+v)} sum_nu dP_u[mu][nu] dPhi_v[nu][i], with the digits
 // of P gathered from the precomputed array through the batch's function list
-// and those of Phi cut from the FP64 slab as it is staged (per-point scales
-// from the collocation kernel). Same tiles and epilogue as k_gemm_rho; one
-// LDS buffer (eight digit planes, 40 KB) with the next step's loads in
-// registers.
+// and those of Phi read from the digit slab the collocation kernel wrote.
+// Same tiles and epilogue as k_gemm_rho; one LDS buffer (eight digit planes,
+// 40 KB) with the next step's loads in registers.
 template <bool GGA>
 __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
@@ -1062,8 +1191,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
     exp_table_init();
-    const double* Phi = (const double*)(scratch + 8 * B.phi_off);
-    const double* pscale = (const double*)(scratch + 8 * B.part_off) + scale_row_off(B);
+    const char* phi = phi_slab(B, R, scratch);
+    const unsigned long long* Phid = (const unsigned long long*)phi;
+    const double* pscale = (const double*)phi + scale_row_off(B);
     const gptr<const int> fl = R.func_list + B.func_off;
     // the epilogue's point (one per lane), loaded now so that its latency hides
     const bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
@@ -1118,10 +1248,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
     const int bn = tid & 63, bk = (tid >> 6) * 8;
     const int fr = frow[ar];
     const gptr<const unsigned long long> Prow = R.Pdig + (size_t)(fr >= 0 ? fr : 0) * nbf;
-    const double inv_sn = 1.0 / pscale[n0 + bn];   // a power of two: exact
     int fc[8];
-    unsigned long long pa[8];
-    double pb[8];
+    unsigned long long pa[8], pb[8];
     auto gload = [&](int ks) {
         const int4 u = *reinterpret_cast<const int4*>(&sfl[ks & 1][ak]);
         const int4 v = *reinterpret_cast<const int4*>(&sfl[ks & 1][ak + 4]);
@@ -1134,7 +1262,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = kb + q;
-            pb[q] = Phi[(size_t)(k < B.nbp ? k : 0) * B.ngp + n0 + bn];
+            pb[q] = Phid[(size_t)(k < B.nbp ? k : 0) * B.ngp + n0 + bn];
         }
     };
     auto sstore = [&](int ks) {
@@ -1150,10 +1278,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
         const int kb = ks * kKB + bk;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            __bf16 e4[4];
-            digits4(kb + q < B.nbp ? pb[q] * inv_sn : 0.0, e4);
+            const unsigned long long w = kb + q < B.nbp ? pb[q] : 0ull;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) d[u][q] = e4[u];
+            for (int u = 0; u < 4; ++u) d[u][q] = bits_bf16((unsigned short)(w >> (16 * u)));
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) *reinterpret_cast<bf16x8*>(&plane(4 + u)[bn][bk]) = d[u];
@@ -1220,7 +1347,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
                             a[u], b[g - u][nb], acc[g][mb][nb], 0, 0, 0);
             }
         }
-        if ((ks & 3) == 3) flush();
+        if ((ks & 7) == 7) flush();
         __syncthreads();
         if (ks + 1 < nk) {
             sstore(ks + 1);
@@ -1253,10 +1380,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
     rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, frow, ex, ey, ez, has, scratch);
 }
 
-// Potential contraction V^j = Z Phi^T + Phi Z^T in split BF16 (Phi stored
-// in FP64, Z in FP32), lower-triangle tiles as in k_syr2k (diagonal tiles
-// reuse their row operands), one LDS buffer with the next step's loads in
-// registers.
+// Potential contraction V^j = Z Phi^T + Phi Z^T in split BF16, lower-
+// triangle tiles as in k_syr2k (diagonal tiles reuse their row operands),
+// one LDS buffer with the next step's loads in registers. Z (FP32) is split
+// as hi + lo; Phi comes from the digit slab: hi = s_i 2^-7 d0 and
+// lo = s_i 2^-15 d1 (exact in BF16), about 15 bits relative to the point's
+// largest function value.
 __global__ __launch_bounds__(256) void k_syr2k_bf16(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
     const ReqDev* __restrict__ reqs, const char* __restrict__ scratch) {
@@ -1272,9 +1401,10 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     while ((I + 1) * (I + 2) / 2 <= lt) ++I;
     while (I * (I + 1) / 2 > lt) --I;
     const int J = lt - I * (I + 1) / 2;
-    const size_t slab = (size_t)B.nbp * B.ngp;
-    const double* Phi = (const double*)(scratch + 8 * B.phi_off);
-    const float* Zm = (const float*)(scratch + 8 * (B.phi_off + (long long)slab));
+    const char* phi = phi_slab(B, R, (char*)scratch);
+    const unsigned long long* Phid = (const unsigned long long*)phi;
+    const float* Zm = (const float*)(scratch + 8 * B.z_off);
+    const double* pscale = (const double*)phi + scale_row_off(B);
     const gptr<const int> fl = func_list + B.func_off;
 
     // ZI, PI, PJ, ZJ, each (hi, lo): one buffer
@@ -1300,14 +1430,17 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
     // operand a: 0 = Z_I, 1 = Phi_I, 2 = Phi_J, 3 = Z_J
     const float* zsrc[2] = {Zm + (size_t)(vI ? rI : 0) * B.ngp, Zm + (size_t)(vJ ? rJ : 0) * B.ngp};
-    const double* psrc[2] = {Phi + (size_t)(vI ? rI : 0) * B.ngp,
-                             Phi + (size_t)(vJ ? rJ : 0) * B.ngp};
+    const unsigned long long* psrc[2] = {Phid + (size_t)(vI ? rI : 0) * B.ngp,
+                                         Phid + (size_t)(vJ ? rJ : 0) * B.ngp};
     // a diagonal tile's column operands are its row operands
     const bool diag = I == J;
     float4 gz[2][2];
-    double2 gp[2][4];
+    ulonglong2 gp[2][4];
+    float sc[8];     // s_i 2^-7 of the step's eight points
     auto gload = [&](int ks) {
         const int k0 = ks * kKB + lk;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sc[q] = (float)(pscale[k0 + q] * 0x1p-7);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && diag) continue;
@@ -1315,17 +1448,32 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
             gz[h][1] = *reinterpret_cast<const float4*>(zsrc[h] + k0 + 4);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                gp[h][q] = *reinterpret_cast<const double2*>(psrc[h] + k0 + 2 * q);
+                gp[h][q] = *reinterpret_cast<const ulonglong2*>(psrc[h] + k0 + 2 * q);
         }
     };
-    auto put = [&](int which, const double (&x)[8], bool valid) {
+    auto put_z = [&](int which, const float4 (&g)[2], bool valid) {
+        const float x[8] = {g[0].x, g[0].y, g[0].z, g[0].w, g[1].x, g[1].y, g[1].z, g[1].w};
         bf16x8 hv, lv;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             __bf16 hq, lq;
-            split_bf16(valid ? x[q] : 0.0, hq, lq);
+            split_bf16(valid ? (double)x[q] : 0.0, hq, lq);
             hv[q] = hq;
             lv[q] = lq;
+        }
+        *reinterpret_cast<bf16x8*>(&tile(which)[lr][lk]) = hv;
+        *reinterpret_cast<bf16x8*>(&tile(which + 1)[lr][lk]) = lv;
+    };
+    auto put_phi = [&](int which, const ulonglong2 (&g)[4], bool valid) {
+        const unsigned long long w[8] = {g[0].x, g[0].y, g[1].x, g[1].y,
+                                         g[2].x, g[2].y, g[3].x, g[3].y};
+        bf16x8 hv, lv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float d0 = (float)bits_bf16((unsigned short)w[q]);
+            const float d1 = (float)bits_bf16((unsigned short)(w[q] >> 16));
+            hv[q] = (__bf16)(valid ? d0 * sc[q] : 0.f);
+            lv[q] = (__bf16)(valid ? d1 * (sc[q] * 0x1p-8f) : 0.f);
         }
         *reinterpret_cast<bf16x8*>(&tile(which)[lr][lk]) = hv;
         *reinterpret_cast<bf16x8*>(&tile(which + 1)[lr][lk]) = lv;
@@ -1335,12 +1483,8 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && diag) continue;
             const bool valid = h == 0 ? vI : vJ;
-            const double z[8] = {gz[h][0].x, gz[h][0].y, gz[h][0].z, gz[h][0].w,
-                                 gz[h][1].x, gz[h][1].y, gz[h][1].z, gz[h][1].w};
-            const double p[8] = {gp[h][0].x, gp[h][0].y, gp[h][1].x, gp[h][1].y,
-                                 gp[h][2].x, gp[h][2].y, gp[h][3].x, gp[h][3].y};
-            put(h == 0 ? 0 : 6, z, valid);
-            put(h == 0 ? 2 : 4, p, valid);
+            put_z(h == 0 ? 0 : 6, gz[h], valid);
+            put_phi(h == 0 ? 2 : 4, gp[h], valid);
         }
     };
 
@@ -1479,7 +1623,7 @@ template <bool GGA, typename T, typename TZ>
 static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                          const int* gpre, const int* spre, int count, int gemm_tiles,
                          int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
-                         bool colloc) {
+                         bool colloc, bool sph) {
     if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
         hipLaunchKernelGGL((k_colloc<T, false>), dim3(count), dim3(256), 0, s, b, reqs, scr);
@@ -1498,7 +1642,8 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
         PhaseScope ps(timer, s, XC_PHASE_FUNCTIONAL);
         hipLaunchKernelGGL((k_func<GGA>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
-        hipLaunchKernelGGL((k_z<TZ>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        if (sph) hipLaunchKernelGGL((k_z<TZ, true>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        else hipLaunchKernelGGL((k_z<TZ, false>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (syr_tiles > 0) {
@@ -1519,7 +1664,7 @@ template <bool GGA>
 static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
                             const int* gpre, const int* spre, int count, int gemm_tiles,
                             int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
-                            bool colloc) {
+                            bool colloc, bool sph) {
     if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
         hipLaunchKernelGGL((k_colloc<double, true>), dim3(count), dim3(256), 0, s, b, reqs, scr);
@@ -1538,7 +1683,8 @@ static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b
         PhaseScope ps(timer, s, XC_PHASE_FUNCTIONAL);
         hipLaunchKernelGGL((k_func<GGA>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
-        hipLaunchKernelGGL((k_z<float>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        if (sph) hipLaunchKernelGGL((k_z<float, true>), dim3(count), dim3(256), 0, s, b, reqs, scr);
+        else hipLaunchKernelGGL((k_z<float, false>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
     if (syr_tiles > 0) {
@@ -1556,11 +1702,11 @@ static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre, int count,
                 int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch,
-                int* d_tmap_i, bool colloc) {
+                int* d_tmap_i, bool colloc, bool sph) {
     if (count == 0) return XC_OK;
     int2* t = (int2*)d_tmap_i;
 #define XC_WAVE_ARGS timer, s, d_wb, d_gpre, d_spre, count, gemm_tiles, syr_tiles, d_reqs, \
-                     scratch, t, colloc
+                     scratch, t, colloc, sph
     if (precision == XC_MIXED_FP32)
         return gga ? launch_wave_t<true, float, float>(XC_WAVE_ARGS)
                    : launch_wave_t<false, float, float>(XC_WAVE_ARGS);
@@ -1635,6 +1781,7 @@ ReqDev make_req(const xc_context* c, const double* dP, double* dV) {
     r.func_shell = (const int*)c->d_fshell.p;
     r.Pdig = (const unsigned long long*)c->pdig.p;
     r.Pscale = (const double*)c->pscale.p;
+    r.phi_base = nullptr;
     r.rho_thresh = c->rho_thresh;
     r.nbf = c->nbf;
     return r;
@@ -1671,7 +1818,7 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
         XC_TRY(launch_wave(&c->timer, c->stream, gga, precision, wb + w.wb_off,
                            gpre + w.pre_off, spre + w.pre_off, w.count, w.gemm_tiles,
                            w.syr_tiles, (const ReqDev*)c->d_req.p, (char*)c->scratch.p,
-                           (int*)c->d_tmap.p, colloc));
+                           (int*)c->d_tmap.p, colloc, c->any_pure));
     if (cacheable) c->phi_cached_kind = kind;
     return launch_finish(&c->timer, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);

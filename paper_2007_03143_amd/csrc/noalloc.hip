@@ -84,7 +84,7 @@ int run_integrate_noalloc(xc_context* c, int functional, int precision, const do
     for (const Wave& w : c->waves)
         XC_TRY(launch_wave(nullptr, c->stream, gga, precision, wb + w.wb_off, gpre + w.pre_off,
                            spre + w.pre_off, w.count, w.gemm_tiles, w.syr_tiles, d_req,
-                           wave_scratch, d_tmap, true));
+                           wave_scratch, d_tmap, true, c->any_pure));
     return launch_finish(nullptr, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);
 }

@@ -49,7 +49,14 @@ struct ShellDev {
     int nprim;
     int prim_off;       // first primitive in the packed exponent/coefficient arrays
     int first_func;     // global index of the shell's first function
+    int pure;           // 1: 2L+1 real solid harmonics (only for L >= 2); 0: Cartesian
+    int pad_;
 };
+
+// Functions of a shell: 2L+1 spherical or (L+1)(L+2)/2 Cartesian.
+__host__ __device__ inline int shell_nfunc(int L, int pure) {
+    return pure ? 2 * L + 1 : (L + 1) * (L + 2) / 2;
+}
 
 // A cuboid cell of points during batching, and a finished batch.
 struct Cell {
@@ -60,14 +67,18 @@ struct Cell {
     double hi[3];
 };
 
-// Per-batch wave scratch: slab 0 = Phi, slab 1 = Z (n_bp x n_gp each, FP64
-// size whatever the storage type), then the rho / grad rho partials.
+// Per-batch wave scratch: the Phi slab (n_bp x n_gp, FP64 size whatever the
+// storage type) and one row of per-point digit scales (split-BF16 mode), the
+// Z slab (n_bp x n_gp), then the rho / grad rho partials. Phi and its scale
+// row may instead live in a request's own Phi store (ReqDev::phi_base).
 constexpr int kSlabs = 2;
 
 // One batch as the integration kernels of a wave read it.
 struct WaveBatch {
-    long long phi_off;  // offset (doubles) of slab 0 of this batch in the wave scratch
-    long long part_off; // offset (doubles) of its density partials
+    long long phi_off;  // offset (doubles) of its Phi slab, from the request's Phi
+                        // store if it has one, else from the wave scratch
+    long long z_off;    // offset (doubles) of its Z slab in the wave scratch
+    long long part_off; // offset (doubles) of its density partials in the wave scratch
     long long pt_off;   // first point
     long long shell_off;// first entry in the shell list
     long long func_off; // first entry in the function list
@@ -79,18 +90,28 @@ struct WaveBatch {
     int nshell;
     int batch;          // batch index within its request
     int req;            // index of the request descriptor (ReqDev) of the launch
+    int flags;          // kSkipColloc: Phi of this batch is already in place
+    int pad_;
 };
+constexpr int kSkipColloc = 1;
 
-// Wave-scratch bytes of one batch: Phi and Z slabs, the density partials
-// (four per row tile and padded point), then one row of per-point digit
-// scales (split-BF16 mode).
+// Bytes of a batch's Phi slab and scale row.
+inline size_t batch_phi_bytes(const WaveBatch& w) {
+    return 8 * ((size_t)w.nbp * w.ngp + w.ngp);
+}
+// Bytes of a batch's Z slab and density partials (four per row tile and
+// padded point).
+inline size_t batch_zpart_bytes(const WaveBatch& w) {
+    return 8 * ((size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
+}
+// Wave-scratch bytes of one batch whose Phi lives in the scratch too.
 inline size_t batch_scratch_bytes(const WaveBatch& w) {
-    return 8 * (kSlabs * (size_t)w.nbp * w.ngp + ((size_t)w.nmt * 4 + 1) * w.ngp);
+    return batch_phi_bytes(w) + batch_zpart_bytes(w);
 }
 
-// Offset (doubles, from the batch's partials) of its per-point digit scales.
+// Offset (doubles, from the batch's Phi slab) of its per-point digit scales.
 __host__ __device__ inline long long scale_row_off(const WaveBatch& w) {
-    return (long long)w.nmt * 4 * w.ngp;
+    return (long long)w.nbp * w.ngp;
 }
 
 // Larger of the batch's density-GEMM and potential-SYR2K tile counts.
@@ -119,6 +140,7 @@ struct ReqDev {
     double* npart;
     const unsigned long long* Pdig;  // split-BF16 mode: four BF16 digits per entry of P
     const double* Pscale;            // and the power-of-two scale of each row of P
+    char* phi_base;                  // the request's Phi store, or null (Phi in the scratch)
     double rho_thresh;
     int nbf;
     int pad_;
@@ -160,12 +182,15 @@ struct xc_context {
     int natoms = 0;
     std::vector<double> atoms4;       // x, y, z, mk_alpha per atom
     int nshells = 0;
-    std::vector<int> shell_atom, shell_L, shell_nprim, prim_off, first_func;
+    std::vector<int> shell_atom, shell_L, shell_nprim, shell_pure, prim_off, first_func;
     std::vector<double> prim_alpha, prim_coef;
     int nbf = 0;
+    bool any_pure = false;            // some shell is spherical
     int n_rad = 0, n_ang = 0;
     std::vector<double> ang;          // n_ang x 4
     double ssf_a = 0.64, screen_eta = 1e-10, rho_thresh = 1e-15;
+    int partition = XC_PARTITION_SSF;
+    std::vector<double> becke_radius;  // empty: no size adjustment
     int batch_max = 512;
     int batch_merge = 1;
     std::vector<int> gatoms;          // parent atoms whose grids are built
@@ -175,6 +200,7 @@ struct xc_context {
     xc::DevBuf d_atoms, d_invR, d_nnhalf, d_shells, d_palpha, d_pcoef, d_ang, d_gatoms;
     xc::DevBuf d_fshell;
     xc::DevBuf d_nbr_idx, d_nbr_R;  // per atom: all atoms by distance
+    xc::DevBuf d_becke_a;           // Becke size adjustments a_AB (natoms x natoms)
 
     // grid and batches
     bool built = false;
@@ -266,11 +292,12 @@ int launch_put_req(hipStream_t s, ReqDev* dst, const ReqDev& v);
 // potential) over count batches whose descriptors are already on the device.
 // d_tmap: room for 2 * max(gemm_tiles, syr_tiles) ints (tile -> batch map).
 // colloc = false skips the collocation kernel: the scratch already holds Phi
-// of these batches in the storage type of this precision.
+// of these batches in the storage type of this precision. sph: some batch of
+// the launch has spherical shells (selects the Z kernel that forms them).
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre,
                 int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
-                char* scratch, int* d_tmap, bool colloc = true);
+                char* scratch, int* d_tmap, bool colloc, bool sph);
 // noalloc.hip: the integration with its wave scratch, tile map and request
 // descriptor in the library's static device array (no allocation).
 int run_integrate_noalloc(xc_context* c, int functional, int precision, const double* dP,

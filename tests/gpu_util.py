@@ -45,7 +45,8 @@ def _progress(stage, done, total):
 
 
 def oracle_integrate(w, functional, atom_mask=None, P=None, **grid_over):
-    g = dict(ssf_a=w.ssf_a, screen_eta=w.screen_eta, rho_thresh=w.rho_thresh)
+    g = dict(ssf_a=w.ssf_a, screen_eta=w.screen_eta, rho_thresh=w.rho_thresh,
+             partition="ssf", becke_radius=None)
     g.update({k: v for k, v in grid_over.items() if k in g})
     n_rad = grid_over.get("n_rad", w.n_rad)
     ang = grid_over.get("ang", w.ang)

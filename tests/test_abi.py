@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_messages():
     import paper_2007_03143_amd as pkg
-    assert pkg.xc_abi_version() == 1
+    assert pkg.xc_abi_version() == 2
     assert pkg.xc_strerror(0) == "ok"
     assert pkg.xc_strerror(pkg.XC_ERR_NOMEM) == "out of device memory"
     assert pkg.xc_strerror(-99) == "unknown error"
@@ -41,6 +41,7 @@ def _water():
 @pytest.mark.parametrize("override,code", [
     (dict(batch_max=8), -1), (dict(batch_max=4096), -1), (dict(ssf_a=1.0), -1),
     (dict(screen_eta=-1.0), -1), (dict(rho_thresh=0.0), -1), (dict(n_rad=0), -1),
+    (dict(partition=5), -1), (dict(partition="becke", becke_radius=[0.6, -0.35, 0.35]), -1),
 ])
 def test_invalid_grid_rejected(override, code):
     import paper_2007_03143_amd as pkg
@@ -78,3 +79,25 @@ def test_invalid_basis_and_functional_rejected():
     with pytest.raises(pkg.XcError) as e:
         pkg.xc_integrate(w.coords, -w.mk_alpha, b, g, "lda", w.P)
     assert e.value.code == pkg.XC_ERR_INVALID_ARG
+
+
+def test_spherical_flags_and_becke_size_limits_rejected():
+    import paper_2007_03143_amd as pkg
+    from workloads import make_basis
+    from workloads.basis import BasisSet
+    w, g = _water()
+    b = w.basis
+    bad = BasisSet(b.shell_atom, b.shell_L, b.shell_nprim, b.prim_alpha, b.prim_coef,
+                   np.full(b.nshells, 2, dtype=np.int32))
+    with pytest.raises(pkg.XcError) as e:
+        pkg.xc_integrate(w.coords, w.mk_alpha, bad, g, "lda", w.P)
+    assert e.value.code == pkg.XC_ERR_INVALID_ARG
+    # 1200 hydrogen atoms on a lattice: above the Becke kernel's atom limit
+    Z = np.ones(1200, dtype=np.int32)
+    X = 3.0 * np.stack(np.meshgrid(np.arange(12), np.arange(10), np.arange(10),
+                                   indexing="ij"), -1).reshape(-1, 3).astype(float)
+    hb = make_basis(Z)
+    grid = dict(g, partition="becke", atom_mask=None)
+    with pytest.raises(pkg.XcError) as e:
+        pkg.xc_integrate(X, np.full(1200, 5.0), hb, grid, "lda", np.zeros((hb.nbf, hb.nbf)))
+    assert e.value.code == pkg.XC_ERR_UNSUPPORTED

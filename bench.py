@@ -1,22 +1,26 @@
 #!/usr/bin/env python
 """Throughput benchmark of the XC integration on one MI355X.
 
-Workload (default): the 64-water cluster, 192 atoms, 1600 Cartesian basis
-functions, 100 x 590 Mura-Knowles x Lebedev grid per atom (11,328,000
-nominal points), PBE, FP64, seeded synthetic inputs.
+Headline workload: the 600-atom polypeptide-like chain (C:N:O:H = 2:1:1:5,
+6280 Cartesian functions with one diffuse shell per atom), 99 x 590
+Mura-Knowles x Lebedev grid per atom (35,046,000 nominal points), PBE, FP64,
+seeded synthetic inputs: one GPU's share of a large system.
 
 One step is the whole path on device-resident inputs: grid points, SSF
 weights, removal of zero-weight points, batching, shell screening, wave
 plan, collocation, X = P Phi with rho/grad rho, functional, Z, and
 V = Z Phi^T + Phi Z^T with scatter-add, mirror and the E_xc/N_e sums.
 value = nominal grid points / step time. The same line reports the warm
-(grid reused, Sec. 2.3.1) rate, with and without Phi kept between
-integrations, the point-weighted histogram of the screened function counts
-n_b, the mixed-precision runs, the roofline of the dominant kernel from
-HIP-event timing inside the timed region, and the CPU oracle timed on a
-bounded sample of the same workload.
+(grid reused, Sec. 2.3.1) rate, the point-weighted histogram of the
+screened function counts n_b, the roofline of the dominant kernel from
+HIP-event timing inside the timed region, the CPU oracle timed on a bounded
+sample of the same workload, and, as secondary keys: the 64-water cluster
+(192 atoms, 100 x 590) in FP64 and in the mixed-precision modes with their
+errors against the FP64 path and against the oracle on a sampled parent
+atom, and the serving stream (continuous batching of 400 requests).
 
-Prints one JSON line on stdout; progress goes to stderr.
+Prints one JSON line on stdout; progress and section wall times go to
+stderr.
 """
 import argparse
 import json
@@ -72,9 +76,10 @@ def nb_histogram(ctx, w, width=128):
 
 def profiled_traffic(kernel, workload, sha):
     """HBM bytes per launch of `kernel` on `workload` from the counter
-    summaries under profiles/ (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
-    a plain copy of known size), used only if they were taken on this exact
-    kernel source; otherwise (None, None)."""
+    summaries under profiles/ (rocprofv3 FETCH_SIZE and WRITE_SIZE averaged
+    over the kernel's dispatches, scaled by a plain copy of known size), used
+    only if they were taken on this exact kernel source; otherwise
+    (None, None)."""
     import glob
     import re
     pat = re.compile(r"^traffic: kernel=(\S+) workload=(\S+) source_sha256=(\S+) "
@@ -92,6 +97,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+class Section:
+    """Logs the wall time of a bench section to stderr."""
+
+    def __init__(self, name):
+        self.name = name
+
+    def __enter__(self):
+        self.t0 = time.perf_counter()
+        log(f"[section {self.name}] start")
+        return self
+
+    def __exit__(self, *exc):
+        log(f"[section {self.name}] {time.perf_counter() - self.t0:.1f} s")
+
+
 def make_workload(name):
     from workloads import cfg_water_cluster, cfg_chain, cfg_water
     if name == "water64":
@@ -103,92 +123,347 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w, functional, stride):
-    """The oracle, as it is, on a strided sample of parent atom 0's grid, with
-    the BLAS threads it gets by default (all cores), and once more with one
-    thread on a sample 8 times sparser."""
-    import oracle
-    try:
-        from threadpoolctl import threadpool_info, threadpool_limits
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threadpool_limits = None
-        threads = os.cpu_count()
-    mask = np.zeros(w.natoms, bool)
-    mask[0] = True
-    n_atom = w.n_rad * w.n_ang
+def roofline(st, timing, steps, w, functional):
+    """Roofline of the dominant phase's kernel from the HIP-event times of
+    the timed region: algorithmic flops per launch (Sum 2 n_b^2 n_g for the
+    density GEMM, Sum 2 n_b (n_b + 1) n_g for the potential SYR2K, from the
+    screened batches) over the average launch duration."""
+    flops = {"density": 2.0 * st["sum_nb2_ng"],
+             "potential": 2.0 * (st["sum_nb2_ng"] + st["sum_nb_ng"])}
+    phase_ms = {k: v["ms"] / steps for k, v in timing.items()}
+    dom = max(phase_ms, key=phase_ms.get)
+    workload_key = f"{w.name}_{functional}_{w.n_rad}x{w.n_ang}_fp64"
+    if dom not in flops:
+        return {"bound": "alu", "kernel": dom, "achieved": None, "peak": None,
+                "unit": None, "frac": None, "traffic": None}, phase_ms
+    launches = timing[dom]["launches"] / steps
+    achieved = flops[dom] / (phase_ms[dom] * 1e-3) / 1e12
+    kname, ksrc = PHASE_KERNEL[dom]
+    sha = source_sha256(ksrc)
+    traffic, tsrc = profiled_traffic(kname, workload_key, sha)
+    return {"bound": "mfma", "kernel": kname, "phase": dom, "achieved": achieved,
+            "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (average over the step's launches)",
+            "traffic_source": tsrc, "kernel_source_sha256": sha,
+            "flops_per_launch": flops[dom] / launches if launches else None,
+            "ms_per_launch": phase_ms[dom] / launches if launches else None,
+            "launches_per_step": launches}, phase_ms
 
-    def run(st):
-        sl = slice(0, None, st)
-        n = len(range(*sl.indices(n_atom)))
-        t0 = time.perf_counter()
-        oracle.integrate(w.coords, w.mk_alpha, w.basis, w.P, functional, w.n_rad, w.ang,
-                         atom_mask=mask, point_slice=sl,
-                         progress=lambda s, d, t: log(f"  oracle {s} {d}/{t}"))
-        return n, time.perf_counter() - t0
 
-    n_sample, dt = run(stride)
-    out = {"value": n_sample / dt, "unit": "grid points/s", "cores": int(threads),
-           "kind": "oracle",
-           "sample": f"{n_sample} points (every {stride}th point of parent atom 0's "
-                     f"{n_atom}-point grid) of the same workload, SSF over all "
-                     f"{w.natoms} atoms, {w.nbf} functions, {functional}; "
-                     f"{dt:.1f} s"}
-    if threadpool_limits is not None:
-        with threadpool_limits(limits=1):
-            n1, dt1 = run(8 * stride)
-        out["value_1_thread"] = n1 / dt1
-        out["sample_1_thread"] = f"{n1} points (every {8 * stride}th), {dt1:.1f} s"
+def fp64_section(w, functional, steps, warmup, wave_gb, batch_merge, singles):
+    """Cold steps (grid build + integration) timed as the contract asks, then
+    warm integrations (grid reused); returns (ctx, P, result dict)."""
+    import torch
+    from paper_2007_03143_amd import XcContext
+    from workloads import grid_spec_dict
+    ctx = XcContext(w.coords, w.mk_alpha, w.basis,
+                    grid_spec_dict(w, batch_merge=batch_merge),
+                    wave_bytes=int(wave_gb * (1 << 30)))
+    P = torch.from_numpy(w.P).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        ctx.build_grid()
+        ctx.integrate(P, functional)
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"  warmup {i + 1}/{warmup} done")
+    st = ctx.stats()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = ctx.timing()
+    ctx.set_timing(False)
+    log(f"  timed {steps} steps in {t1 - t0:.3f} s")
+    ms_step = (t1 - t0) * 1e3 / steps
+    n_nom = w.n_points_nominal
+
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(steps):
+        ctx.integrate(P, functional)
+    torch.cuda.synchronize()
+    ms_warm = (time.perf_counter() - t2) * 1e3 / steps
+    EN = ctx.EN.cpu().numpy().copy()
+    V = ctx.V.cpu().numpy()
+    log(f"  warm {ms_warm:.1f} ms/step; E_xc {EN[0]!r} N_e {EN[1]!r}")
+    per = []
+    for i in range(singles):
+        ta = time.perf_counter()
+        ctx.integrate(P, functional)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - ta) * 1e3)
+    warm = {"value": n_nom / (ms_warm * 1e-3), "ms_per_step": ms_warm,
+            "step": "integration with the grid reused",
+            "median_ms_single": float(np.median(per)) if per else None,
+            "single_runs": len(per)}
+    if st["n_waves"] == 1:
+        ctx.set_phi_cache(True)
+        ctx.integrate(P, functional)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for i in range(steps):
+            ctx.integrate(P, functional)
+        torch.cuda.synchronize()
+        ms_cache = (time.perf_counter() - t2) * 1e3 / steps
+        ENc = ctx.EN.cpu().numpy()
+        ctx.set_phi_cache(False)
+        warm["phi_cache"] = {"value": n_nom / (ms_cache * 1e-3), "ms_per_step": ms_cache,
+                             "same_E_N": bool(np.array_equal(ENc, EN))}
+        log(f"  warm, Phi cached: {ms_cache:.1f} ms/step")
+    else:
+        warm["phi_cache"] = {"active": False,
+                             "note": f"{st['n_waves']} waves: Phi is only kept for "
+                                     "one-wave plans"}
+    roof, phase_ms = roofline(st, timing, steps, w, functional)
+    contract_ms = phase_ms["density"] + phase_ms["potential"]
+    fl = 2.0 * st["sum_nb2_ng"] + 2.0 * (st["sum_nb2_ng"] + st["sum_nb_ng"])
+    res = {"value": n_nom / (ms_step * 1e-3), "ms_per_step": ms_step, "steps": steps,
+           "warmup": warmup,
+           "config": {"workload": f"{w.name} {functional} {w.n_rad}x{w.n_ang}",
+                      "natoms": w.natoms, "nbf": w.nbf, "n_points_nominal": n_nom,
+                      "n_points_kept": st["n_points"], "n_batches": st["n_batches"],
+                      "mean_nb_point_weighted": st["sum_nb_ng"] / max(st["n_points"], 1),
+                      "max_nb": st["max_nb"], "n_waves": st["n_waves"],
+                      "precision": "fp64", "parallelism": "single GPU",
+                      "batch_merge": batch_merge,
+                      "step": "grid build + weights + batching + screening + integration"},
+           "warm": warm,
+           "nb_histogram_point_weighted": nb_histogram(ctx, w),
+           "ssf": {"points_per_s": n_nom / (phase_ms["weights"] * 1e-3),
+                   "pair_terms_plain_equiv_per_s":
+                       n_nom * w.natoms * (w.natoms - 1) / (phase_ms["weights"] * 1e-3),
+                   "note": "nominal points, and the N_A (N_A - 1) pair terms per point "
+                           "of the plain partition formula, per second of the weights "
+                           "phase"},
+           "phase_ms_per_step": phase_ms,
+           "contractions_tflops": fl / (contract_ms * 1e-3) / 1e12,
+           "roofline": roof,
+           "E_xc": float(EN[0]), "N_e": float(EN[1]),
+           "V_symmetric": bool(np.array_equal(V, V.T))}
+    return ctx, P, res, (EN, V, ms_warm)
+
+
+def mixed_section(ctx, P, w, functional, precs, ref, steps):
+    """Warm integrations in each mixed mode: speedup over FP64 warm, errors
+    against the FP64 path on the whole workload, and the phase split."""
+    import torch
+    EN, V, ms_warm = ref
+    n_nom = w.n_points_nominal
+    out = {}
+    for prec in precs:
+        ctx.integrate(P, functional, prec)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for i in range(steps):
+            ctx.integrate(P, functional, prec)
+        torch.cuda.synchronize()
+        ms_m = (time.perf_counter() - t4) * 1e3 / steps
+        ENm = ctx.EN.cpu().numpy()
+        Vm = ctx.V.cpu().numpy()
+        ctx.set_timing(True)
+        for i in range(3):
+            ctx.integrate(P, functional, prec)
+        torch.cuda.synchronize()
+        tm = ctx.timing()
+        ctx.set_timing(False)
+        out[prec] = {"warm_value": n_nom / (ms_m * 1e-3), "warm_ms_per_step": ms_m,
+                     "phase_ms_per_step": {k: v["ms"] / 3 for k, v in tm.items()
+                                           if v["launches"]},
+                     "speedup_vs_fp64_warm": ms_warm / ms_m,
+                     "dE_xc_vs_fp64": float(ENm[0] - EN[0]),
+                     "dN_e_vs_fp64": float(ENm[1] - EN[1]),
+                     "max_dV_vs_fp64": float(np.abs(Vm - V).max())}
+        log(f"  {prec}: {ms_m:.1f} ms/step ({ms_warm / ms_m:.2f}x), "
+            f"dE vs fp64 {ENm[0] - EN[0]:.3e}")
     return out
 
 
-def serving_run(n_req, seed=5, load=0.7, saturation=None):
-    """The serving stream: n_req requests (1-100 waters, LDA/PBE, 6-12 SCF
-    iterations, 75 x 302 grid), densities made on the device. Arrivals are
-    Poisson at `load` x the stream's closed-loop saturation rate, which is
-    measured first (all requests submitted at once) unless given."""
+def oracle_atom_check(w, functional, atom, precs):
+    """Errors against the FP64 oracle on one parent atom's grid (the
+    partition over all atoms), for FP64 and every mixed mode."""
     import torch
-    from paper_2007_03143_amd.serving import ServeRequest, DeviceDensities, serve
+    import oracle
+    from paper_2007_03143_amd import XcContext
+    from workloads import grid_spec_dict
+    mask = np.zeros(w.natoms, np.uint8)
+    mask[atom] = 1
+    t0 = time.perf_counter()
+    Eo, No, Vo = oracle.integrate(w.coords, w.mk_alpha, w.basis, w.P, functional, w.n_rad,
+                                  w.ang, atom_mask=mask)
+    t_or = time.perf_counter() - t0
+    ctx = XcContext(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w, atom_mask=mask))
+    P = torch.from_numpy(w.P).cuda()
+    out = {"atom": atom, "element_Z": int(w.mol.Z[atom]),
+           "oracle_seconds": round(t_or, 1)}
+    try:
+        for prec in ["fp64"] + list(precs):
+            V, EN = ctx.integrate(P, functional, prec)
+            torch.cuda.synchronize()
+            en = EN.cpu().numpy()
+            Vh = V.cpu().numpy()
+            out[prec] = {"dE_xc": float(en[0] - Eo), "dN_e": float(en[1] - No),
+                         "max_dV": float(np.abs(Vh - Vo).max())}
+            log(f"  atom {atom} {prec}: dE vs oracle {en[0] - Eo:.3e}")
+    finally:
+        ctx.close()
+    return out
+
+
+def cpu_baseline(w, functional, atom, stride, extrapolate):
+    """The oracle, as it is, on a strided sample of one parent atom's grid,
+    with the BLAS threads it gets by default (all cores)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    mask = np.zeros(w.natoms, bool)
+    mask[atom] = True
+    n_atom = w.n_rad * w.n_ang
+    sl = slice(0, None, stride)
+    n = len(range(*sl.indices(n_atom)))
+    t0 = time.perf_counter()
+    oracle.integrate(w.coords, w.mk_alpha, w.basis, w.P, functional, w.n_rad, w.ang,
+                     atom_mask=mask, point_slice=sl)
+    dt = time.perf_counter() - t0
+    rate = n / dt
+    out = {"value": rate, "unit": "grid points/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n} points (every {stride}th point of parent atom {atom}'s "
+                     f"{n_atom}-point grid) of the same workload, SSF over all "
+                     f"{w.natoms} atoms, {w.nbf} functions, {functional}; {dt:.1f} s"}
+    if extrapolate:
+        out["extrapolated_whole_workload_s"] = w.n_points_nominal / rate
+        out["note"] = ("rate measured on the sample; the whole workload's oracle time is "
+                       "extrapolated from it (nominal points / rate)")
+    return out
+
+
+# ---------------------------------------------------------------- serving ----
+def _overlap_job(args):
+    """Worker: the analytic overlap S of one request's basis (input
+    generation, no method arithmetic)."""
+    from workloads.basis import overlap_matrix
+    basis, coords = args
+    return overlap_matrix(basis, coords)
+
+
+def _oracle_job(args):
+    """Worker: the oracle on one checked request (whole grid or one parent
+    atom), with a few BLAS threads."""
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=args["threads"])
+    except Exception:
+        lim = None
+    import oracle
+    E, N, V = oracle.integrate(args["coords"], args["mk_alpha"], args["basis"], args["P"],
+                               args["functional"], args["n_rad"], args["ang"],
+                               atom_mask=args["atom_mask"])
+    return E, N, V
+
+
+def serving_run(n_req, s_pool_result, seed=5, load=0.7, n_sat=100, check_frac=0.05,
+                small_atoms=12):
+    """The serving stream: n_req requests (1-100 waters, LDA/PBE, 6-12 SCF
+    iterations, 75 x 302 grid), densities made on the device. The stream's
+    closed-loop saturation rate (points/s) is measured on its first n_sat
+    requests (all submitted at once); arrivals are then Poisson at `load` x
+    that rate over all n_req requests. Accuracy: a seeded check_frac of the
+    requests, drawn over all sizes, each at a seeded SCF iteration, against the
+    oracle: requests of up to small_atoms atoms on their whole grid; larger
+    ones through a twin request (same molecule and densities, the grid of one
+    seeded parent atom) served in the same stream and compared with the oracle
+    on that atom's grid. The oracle runs in worker processes while the GPU
+    serves."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import torch
+    from paper_2007_03143_amd.serving import DeviceDensities, ServeRequest, serve
     from workloads import grid_spec_dict
     from workloads.configs import serving_stream
-    import oracle
     stream = serving_stream(n_req, seed=seed)
+    S_all = s_pool_result()
     mean_pts = np.mean([w.n_points_nominal * n for w, n, _ in stream])
 
-    def requests(arrivals):
-        return [ServeRequest(w.coords, w.mk_alpha, w.basis, grid_spec_dict(w), w.functional,
-                             DeviceDensities(w.nbf, w.n_occ, n_iter, dseed), arrival=float(t),
-                             name=w.name, n_points_nominal=w.n_points_nominal)
-                for (w, n_iter, dseed), t in zip(stream, arrivals)]
+    def make(i, arrival, atom_mask=None):
+        w, n_iter, dseed = stream[i]
+        g = grid_spec_dict(w, atom_mask=atom_mask)
+        npts = w.n_points_nominal if atom_mask is None else w.n_rad * w.n_ang
+        return ServeRequest(w.coords, w.mk_alpha, w.basis, g, w.functional,
+                            DeviceDensities(S_all[i], w.n_occ, n_iter, dseed),
+                            arrival=float(arrival), name=w.name, n_points_nominal=npts)
 
-    if saturation is None:
-        closed = serve(requests(np.zeros(n_req)), wave_bytes=2 << 30)
-        saturation = closed["points_per_s"]
-        log(f"serving: closed-loop {saturation / 1e6:.1f} Mpts/s")
+    n_sat = min(n_sat, n_req)
+    closed = serve([make(i, 0.0) for i in range(n_sat)], wave_bytes=2 << 30)
+    saturation = closed["points_per_s"]
+    log(f"  closed-loop on {n_sat} requests: {saturation / 1e6:.1f} Mpts/s")
     lam = load * saturation / mean_pts
     rng = np.random.default_rng([seed, 99])
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
     arrivals -= arrivals[0]
-    reqs = requests(arrivals)
-    small = [i for i, (w, _, _) in enumerate(stream) if w.natoms <= 12]
-    n_check = max(1, int(round(0.05 * n_req)))
-    check = sorted(rng.choice(small, size=min(n_check, len(small)), replace=False).tolist()) \
-        if small else []
-    summary = serve(reqs, wave_bytes=2 << 30, keep_v=lambda i: i in check)
-    checks = []
+    reqs = [make(i, arrivals[i]) for i in range(n_req)]
+    # checked requests and iterations, drawn over the whole stream
+    n_check = max(1, int(round(check_frac * n_req)))
+    check = sorted(rng.choice(n_req, size=n_check, replace=False).tolist())
+    jobs, twins = [], []
     for i in check:
-        r = reqs[i]
-        P0 = r.densities.host(0)
-        r.densities.release()
-        Eo, No, Vo = oracle.integrate(r.coords, r.mk_alpha, r.basis, P0, r.functional,
-                                      r.grid["n_rad"], r.grid["ang"])
-        E, N, V = r.results[0]
-        checks.append({"request": i, "name": r.name, "dE_xc": E - Eo, "dN_e": N - No,
-                       "max_dV": float(np.abs(V - Vo).max())})
+        w, n_iter, _ = stream[i]
+        k = int(rng.integers(0, n_iter))
+        P_k = reqs[i].densities.host(k)
+        reqs[i].densities.release()
+        if w.natoms <= small_atoms:
+            mask = None
+        else:
+            mask = np.zeros(w.natoms, np.uint8)
+            mask[int(rng.integers(0, w.natoms))] = 1
+            twin = make(i, arrivals[i], atom_mask=mask)
+            twin.name = w.name + "_twin"
+            twins.append(twin)
+        jobs.append({"request": i, "k": k, "mask": mask, "twin": len(twins) - 1 if mask is not None else None,
+                     "args": {"coords": w.coords, "mk_alpha": w.mk_alpha, "basis": w.basis,
+                              "P": P_k, "functional": w.functional, "n_rad": w.n_rad,
+                              "ang": w.ang, "atom_mask": mask, "threads": 2}})
+    torch.cuda.empty_cache()
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=6, mp_context=ctx) as ex:
+        futs = [ex.submit(_oracle_job, j["args"]) for j in jobs]
+        checked_v = {(j["request"], j["k"]) for j in jobs if j["mask"] is None}
+        twin_ids = set(range(n_req, n_req + len(twins)))
+        summary = serve(reqs + twins, wave_bytes=2 << 30,
+                        keep_v=lambda i: (i in twin_ids) or any(r == i for r, _ in checked_v),
+                        exclude=twin_ids)
+        log(f"  served {summary['integrations']} integrations in {summary['wall_s']:.1f} s; "
+            "waiting for the oracle checks")
+        checks = []
+        for j, f in zip(jobs, futs):
+            Eo, No, Vo = f.result()
+            r = reqs[j["request"]] if j["mask"] is None else twins[j["twin"]]
+            E, N, V = r.results[j["k"]]
+            w = stream[j["request"]][0]
+            checks.append({"request": j["request"], "name": w.name, "atoms": w.natoms,
+                           "iteration": j["k"],
+                           "compared": "whole grid" if j["mask"] is None else
+                                       f"twin on parent atom {int(np.nonzero(j['mask'])[0][0])}",
+                           "dE_xc": E - Eo, "dN_e": N - No,
+                           "max_dV": float(np.abs(V - Vo).max())})
+    worst = max(max(abs(c["dE_xc"]), abs(c["dN_e"]), c["max_dV"]) for c in checks)
     summary.update({"requests": n_req, "load": load, "arrival_rate_per_s": lam,
                     "saturation_points_per_s": saturation,
+                    "saturation_measured_on": f"first {n_sat} requests, closed loop",
                     "mean_points_per_request": mean_pts, "oracle_checks": checks,
-                    "grid": "75x302", "wave_bytes": 2 << 30})
+                    "oracle_checks_worst_abs": worst,
+                    "twin_requests_excluded_from_latency": len(twins),
+                    "grid": "75x302", "wave_bytes": 2 << 30,
+                    "density": "P_0 = 2 C C^T with S-orthonormal C, P_k = P_0 + delta_k"})
     return summary
 
 
@@ -197,20 +472,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="water64")
+    ap.add_argument("--workload", default="chain600")
+    ap.add_argument("--secondary", default="water64",
+                    help="second workload (FP64 and the mixed modes); empty: skip")
     ap.add_argument("--wave-gb", type=float, default=0.0)
-    ap.add_argument("--cpu-stride", type=int, default=2)
+    ap.add_argument("--cpu-stride", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-merge", type=int, default=1)
-    ap.add_argument("--mixed", default="fp32,fp32v,bf16x3")
-    ap.add_argument("--serving", type=int, default=40,
+    ap.add_argument("--mixed", default="fp32,bf16,fp32v")
+    ap.add_argument("--mixed-steps", type=int, default=5)
+    ap.add_argument("--oracle-atom", type=int, default=0,
+                    help="parent atom of the secondary workload checked against the "
+                         "oracle in every precision (-1: skip)")
+    ap.add_argument("--serving", type=int, default=400,
                     help="requests in the serving stream (0: skip)")
-    ap.add_argument("--serving-loads", default="0.7",
-                    help="arrival rates as fractions of the closed-loop rate; the first "
-                         "is reported as 'serving', all of them in 'serving_sweep'")
+    ap.add_argument("--serving-load", type=float, default=0.7,
+                    help="arrival rate as a fraction of the closed-loop rate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 3 times (a plain "
                          "copy kernel of known size for scaling HBM byte counters)")
+    ap.add_argument("--only-fp64", action="store_true",
+                    help="only the headline FP64 section (for profiling runs)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -230,185 +512,66 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2007_03143_amd import XcContext
-    from workloads import grid_spec_dict
 
-    log(f"building workload {args.workload}")
-    w, functional = make_workload(args.workload)
-    ctx = XcContext(w.coords, w.mk_alpha, w.basis,
-                    grid_spec_dict(w, batch_merge=args.batch_merge),
-                    wave_bytes=int(args.wave_gb * (1 << 30)))
-    P = torch.from_numpy(w.P).cuda()
-    torch.cuda.synchronize()
+    # the overlap matrices of the serving requests (input generation) are
+    # computed in worker processes while the GPU sections run
+    s_futs = None
+    if args.serving > 0 and not args.only_fp64:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        from workloads.configs import serving_stream
+        st_list = serving_stream(args.serving, seed=5)
+        ex = cf.ProcessPoolExecutor(max_workers=8, mp_context=mp.get_context("spawn"))
+        s_futs = (ex, [ex.submit(_overlap_job, (w.basis, w.coords)) for w, _, _ in st_list])
 
-    def step():
-        ctx.build_grid()
-        ctx.integrate(P, functional)
+    with Section(f"headline {args.workload} fp64"):
+        w, functional = make_workload(args.workload)
+        ctx, P, head, ref = fp64_section(w, functional, args.steps, args.warmup, args.wave_gb,
+                                         args.batch_merge, singles=5)
+        ctx.close()
+        del P
+        torch.cuda.empty_cache()
+    out = {"metric": METRIC, "value": head["value"], "unit": "grid points/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic"}
+    out.update({k: head[k] for k in head if k not in ("value", "ms_per_step", "steps",
+                                                        "warmup")})
+    if args.only_fp64:
+        print(json.dumps(out), flush=True)
+        return
 
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    st = ctx.stats()
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timing = ctx.timing()
-    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    n_nom = w.n_points_nominal
-    value = n_nom / (ms_step * 1e-3)
+    if args.secondary:
+        with Section(f"secondary {args.secondary}"):
+            w2, f2 = make_workload(args.secondary)
+            ctx2, P2, sec, ref2 = fp64_section(w2, f2, args.steps, min(args.warmup, 3),
+                                               0.0, args.batch_merge, singles=10)
+            precs = [p for p in args.mixed.split(",") if p]
+            sec["mixed"] = mixed_section(ctx2, P2, w2, f2, precs, ref2, args.mixed_steps)
+            ctx2.close()
+            del P2
+            torch.cuda.empty_cache()
+            if args.oracle_atom >= 0:
+                sec["mixed_vs_oracle_sampled_atom"] = oracle_atom_check(
+                    w2, f2, args.oracle_atom, precs)
+            sec.pop("nb_histogram_point_weighted", None)
+            out["secondary"] = sec
 
-    # warm: grid, weights, batches and screening lists reused
-    ctx.set_timing(False)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for i in range(args.steps):
-        ctx.integrate(P, functional)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    ms_warm = (t3 - t2) * 1e3 / args.steps
-    EN = ctx.EN.cpu().numpy()
-    V = ctx.V.cpu().numpy()
-    log(f"warm {ms_warm:.1f} ms/step; E_xc {EN[0]!r} N_e {EN[1]!r}")
-
-    # per-integration times (synchronised one by one) for the median
-    per = []
-    for i in range(max(args.steps, 10)):
-        ta = time.perf_counter()
-        ctx.integrate(P, functional)
-        torch.cuda.synchronize()
-        per.append((time.perf_counter() - ta) * 1e3)
-    ms_warm_med = float(np.median(per))
-
-    # warm with Phi kept between integrations (one-wave plans only)
-    ctx.set_phi_cache(True)
-    ctx.integrate(P, functional)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for i in range(args.steps):
-        ctx.integrate(P, functional)
-    torch.cuda.synchronize()
-    ms_cache = (time.perf_counter() - t2) * 1e3 / args.steps
-    ENc = ctx.EN.cpu().numpy()
-    ctx.set_phi_cache(False)
-    log(f"warm, Phi cached: {ms_cache:.1f} ms/step")
-    nb_hist = nb_histogram(ctx, w)
-
-    # mixed precision: FP32 collocation and contractions, FP64 functional/sums
-    mixed = {}
-    for prec in args.mixed.split(",") if args.mixed else []:
-        ctx.integrate(P, functional, prec)
-        torch.cuda.synchronize()
-        t4 = time.perf_counter()
-        for i in range(args.steps):
-            ctx.integrate(P, functional, prec)
-        torch.cuda.synchronize()
-        ms_m = (time.perf_counter() - t4) * 1e3 / args.steps
-        ENm = ctx.EN.cpu().numpy()
-        Vm = ctx.V.cpu().numpy()
-        # phase split of the same integration, timed separately with HIP events
-        ctx.set_timing(True)
-        for i in range(args.steps):
-            ctx.integrate(P, functional, prec)
-        torch.cuda.synchronize()
-        tm = ctx.timing()
-        ctx.set_timing(False)
-        mixed[prec] = {"warm_value": n_nom / (ms_m * 1e-3), "warm_ms_per_step": ms_m,
-                       "phase_ms_per_step": {k: v["ms"] / args.steps for k, v in tm.items()
-                                             if v["launches"]},
-                       "speedup_vs_fp64_warm": ms_warm / ms_m,
-                       "dE_xc_vs_fp64": float(ENm[0] - EN[0]),
-                       "dN_e_vs_fp64": float(ENm[1] - EN[1]),
-                       "max_dV_vs_fp64": float(np.abs(Vm - V).max())}
-        log(f"{prec}: {ms_m:.1f} ms/step, dE {ENm[0] - EN[0]:.3e}")
-
-    # roofline of the dominant kernel (HIP events inside the timed region)
-    flops = {"density": 2.0 * st["sum_nb2_ng"],
-             "potential": 2.0 * (st["sum_nb2_ng"] + st["sum_nb_ng"])}
-    phase_ms = {k: v["ms"] / args.steps for k, v in timing.items()}
-    dom = max(phase_ms, key=phase_ms.get)
-    workload_key = f"{w.name}_{functional}_{w.n_rad}x{w.n_ang}_fp64"
-    if dom in flops:
-        launches = timing[dom]["launches"] / args.steps
-        achieved = flops[dom] / (phase_ms[dom] * 1e-3) / 1e12
-        kname, ksrc = PHASE_KERNEL[dom]
-        sha = source_sha256(ksrc)
-        traffic, tsrc = profiled_traffic(kname, workload_key, sha) if launches == 1 else (None, None)
-        roof = {"bound": "mfma", "kernel": kname, "phase": dom, "achieved": achieved,
-                "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": traffic,
-                "traffic_unit": "HBM bytes per launch",
-                "traffic_source": tsrc, "kernel_source_sha256": sha,
-                "flops_per_launch": flops[dom] / launches if launches else None,
-                "ms_per_launch": phase_ms[dom] / launches if launches else None,
-                "launches_per_step": launches}
-    else:
-        roof = {"bound": "alu", "kernel": dom, "achieved": None,
-                "peak": None, "unit": None, "frac": None, "traffic": None}
-    contract_ms = phase_ms["density"] + phase_ms["potential"]
-    both = (flops["density"] + flops["potential"]) / (contract_ms * 1e-3) / 1e12
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "grid points/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{w.name} {functional} {w.n_rad}x{w.n_ang}",
-                   "natoms": w.natoms, "nbf": w.nbf, "n_points_nominal": n_nom,
-                   "n_points_kept": st["n_points"], "n_batches": st["n_batches"],
-                   "mean_nb_point_weighted": st["sum_nb_ng"] / max(st["n_points"], 1),
-                   "max_nb": st["max_nb"], "n_waves": st["n_waves"],
-                   "precision": "fp64", "parallelism": "single GPU",
-                   "batch_merge": args.batch_merge,
-                   "step": "grid build + weights + batching + screening + integration"},
-        "warm": {"value": n_nom / (ms_warm * 1e-3), "ms_per_step": ms_warm,
-                 "step": "integration with the grid reused",
-                 "median_ms_single": ms_warm_med, "single_runs": len(per),
-                 "phi_cache": {"value": n_nom / (ms_cache * 1e-3), "ms_per_step": ms_cache,
-                               "active": st["n_waves"] == 1,
-                               "same_E_N": bool(np.array_equal(ENc, EN))}},
-        "nb_histogram_point_weighted": nb_hist,
-        "ssf": {"points_per_s": n_nom / (phase_ms["weights"] * 1e-3),
-                "pair_terms_plain_equiv_per_s":
-                    n_nom * w.natoms * (w.natoms - 1) / (phase_ms["weights"] * 1e-3),
-                "note": "nominal points, and the N_A (N_A - 1) pair terms per point "
-                        "of the plain partition formula, per second of the weights phase"},
-        "phase_ms_per_step": phase_ms,
-        "mixed": mixed,
-        "contractions_tflops": both,
-        "roofline": roof,
-        "E_xc": float(EN[0]), "N_e": float(EN[1]),
-        "V_symmetric": bool(np.array_equal(V, V.T)),
-    }
-    ctx.close()
-    del P
-    torch.cuda.empty_cache()
     if args.serving > 0:
-        loads = [float(x) for x in args.serving_loads.split(",")]
-        sweep = []
-        sat = None
-        for ld in loads:
-            log(f"serving stream of {args.serving} requests at {ld} x the closed-loop rate")
-            res = serving_run(args.serving, load=ld, saturation=sat)
-            sat = res["saturation_points_per_s"]
-            log(f"serving: p50 {res['latency_p50_ms']:.1f} ms p99 {res['latency_p99_ms']:.1f} ms")
-            sweep.append(res)
-        out["serving"] = sweep[0]
-        if len(sweep) > 1:
-            out["serving_sweep"] = [
-                {k: r[k] for k in ("load", "arrival_rate_per_s", "saturation_points_per_s",
-                                   "points_per_s",
-                                   "latency_p50_ms", "latency_p99_ms",
-                                   "request_latency_p50_s", "request_latency_p99_s",
-                                   "wall_s", "integrations")} for r in sweep]
+        with Section(f"serving {args.serving} requests"):
+            ex, futs = s_futs
+            res = serving_run(args.serving, lambda: [f.result() for f in futs],
+                              load=args.serving_load)
+            ex.shutdown()
+            log(f"  serving: p50 {res['latency_p50_ms']:.1f} ms p99 "
+                f"{res['latency_p99_ms']:.1f} ms, worst oracle check "
+                f"{res['oracle_checks_worst_abs']:.2e}")
+            out["serving"] = res
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a sample)")
-        out["cpu_baseline"] = cpu_baseline(w, functional, args.cpu_stride)
+        with Section("cpu baseline (oracle on a sample)"):
+            atom = w.natoms // 2
+            out["cpu_baseline"] = cpu_baseline(w, functional, atom, args.cpu_stride,
+                                               extrapolate=True)
     print(json.dumps(out), flush=True)
 
 

@@ -1,17 +1,25 @@
 // Continuous-batching engine: many XC integrations (one per SCF iteration of
 // many molecules) share the device. Requests are admitted by device-memory
 // footprint; an admitted request's grid, weights, batches and screening
-// lists stay on the device across its iterations (grid reuse, Sec. 2.3.1);
-// every step co-batches the pending grid batches of all in-flight
-// integrations into the same launches (Alg. 4 over a mixed batch set).
+// lists stay on the device across its iterations (grid reuse, Sec. 2.3.1),
+// and so, when the budget allows, do its collocation matrices Phi^j (they
+// depend on the grid and the basis only); every step co-batches the pending
+// grid batches of all in-flight integrations into the same launches (Alg. 4
+// over a mixed batch set). Grids of newly admitted requests are built by a
+// builder thread on a stream of its own, so building never holds up the
+// steps of the requests already running.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "xc_internal.hpp"
@@ -38,47 +46,67 @@ struct Request {
     int precision = XC_FP64;
     size_t est_bytes = 0;
     size_t bytes = 0;
+    bool building = false;      // handed to the builder thread
+    bool est_charged = false;   // est_bytes counted in the engine's used bytes
+    std::atomic<bool> built{false};  // set by the builder thread when done
+    int build_rc = XC_OK;       // its result (valid once built)
     bool admitted = false;
     bool released = false;
     int error = XC_OK;          // set when the request cannot be admitted
     std::string error_msg;
     std::deque<Integration*> queued;
     Integration* active = nullptr;
+    // collocation matrices kept across the request's integrations
+    bool cache = false;
+    bool phi_ready = false;     // the first integration has written them
+    DevBuf phi_store;
+    std::vector<long long> phi_offs;  // per batch, doubles from phi_store
 };
 
 }  // namespace xc
 
 struct xc_engine {
     hipStream_t stream = nullptr;
+    int device = 0;
     size_t budget = 0;
     size_t wave_bytes = 0;
     size_t used = 0;
+    bool cache_phi = false;
     xc::DevBuf scratch, d_wb, d_gpre, d_spre, d_reqs, d_tmap;
     std::map<long long, xc::Request*> reqs;
     std::deque<long long> waiting;
     std::map<long long, xc::Integration*> tickets;
     long long next_req = 1, next_ticket = 1;
-    long long steps = 0, batches_launched = 0, completed = 0;
+    long long steps = 0, batches_launched = 0, completed = 0, colloc_batches = 0;
     xc::PhaseTimer timer;
+    // builder thread
+    hipStream_t build_stream = nullptr;
+    std::thread builder;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<xc::Request*> build_q;
+    bool stop = false;
 };
 
 namespace xc {
 
 int build_grid(xc_context* c);
 
-static int admit(xc_engine* e) {
-    for (auto it = e->waiting.begin(); it != e->waiting.end();) {
-        Request* r = e->reqs[*it];
-        if (r->released) {
-            it = e->waiting.erase(it);
-            continue;
-        }
-        if (e->used + r->est_bytes > e->budget) {
-            ++it;
-            continue;
+// The builder thread: builds the grids of admitted requests, one at a time,
+// on its own stream (the build synchronises that stream, not the engine's).
+static void builder_main(xc_engine* e) {
+    (void)hipSetDevice(e->device);
+    for (;;) {
+        Request* r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(e->mu);
+            e->cv.wait(lk, [&] { return e->stop || !e->build_q.empty(); });
+            if (e->stop) return;
+            r = e->build_q.front();
+            e->build_q.pop_front();
         }
         xc_context* c = r->ctx;
-        c->external_scratch = true;
+        c->stream = e->build_stream;
         int rc = build_grid(c);
         if (rc == XC_OK) {
             release_build_temporaries(c);
@@ -92,19 +120,80 @@ static int admit(xc_engine* e) {
             rc = dev_reserve(c->pdig, 8 * (size_t)c->nbf * c->nbf);
             if (rc == XC_OK) rc = dev_reserve(c->pscale, 8 * (size_t)c->nbf);
         }
+        if (rc == XC_OK) {
+            hipError_t st = hipStreamSynchronize(e->build_stream);
+            if (st != hipSuccess) rc = hip_fail(st, "hipStreamSynchronize(build stream)");
+        }
+        if (rc != XC_OK) r->error_msg = xc_last_error();
+        c->stream = e->stream;
+        r->build_rc = rc;
+        r->built.store(true, std::memory_order_release);
+    }
+}
+
+// Hand waiting requests whose estimated footprint fits to the builder, and
+// finish the admission of those whose grids are built: the estimate is
+// replaced by the actual bytes, and the Phi store is added when caching is
+// on and the budget allows it.
+static int admit(xc_engine* e) {
+    for (auto it = e->waiting.begin(); it != e->waiting.end();) {
+        Request* r = e->reqs[*it];
+        if (r->released) {
+            it = e->waiting.erase(it);
+            continue;
+        }
+        if (!r->building) {
+            if (e->used + r->est_bytes > e->budget) {
+                ++it;
+                continue;
+            }
+            r->building = true;
+            r->est_charged = true;
+            e->used += r->est_bytes;
+            {
+                std::lock_guard<std::mutex> lk(e->mu);
+                e->build_q.push_back(r);
+            }
+            e->cv.notify_one();
+            ++it;
+            continue;
+        }
+        if (!r->built.load(std::memory_order_acquire)) {
+            ++it;
+            continue;
+        }
+        xc_context* c = r->ctx;
+        e->used -= std::min(e->used, r->est_bytes);
+        r->est_charged = false;
+        int rc = r->build_rc;
         if (rc != XC_OK) {
             // the request can never run: it leaves the queue with its device
             // memory released, and its integrations report the error
             r->error = rc;
-            r->error_msg = xc_last_error();
             for (Integration* in : r->queued) in->error = rc;
             r->queued.clear();
             xc_context_destroy(c);
             r->ctx = nullptr;
             it = e->waiting.erase(it);
-            return rc;
+            return fail(rc, r->error_msg);
         }
         r->bytes = device_bytes(c);
+        if (e->cache_phi) {
+            size_t store = 0;
+            r->phi_offs.clear();
+            for (const WaveBatch& w : c->h_wb) {
+                r->phi_offs.push_back((long long)(store / 8));
+                store += batch_phi_bytes(w);
+            }
+            if (e->used + r->bytes + store <= e->budget &&
+                dev_reserve(r->phi_store, std::max<size_t>(store, 8)) == XC_OK) {
+                r->cache = true;
+                r->bytes += r->phi_store.cap;
+            } else {
+                (void)hipGetLastError();
+                r->phi_offs.clear();
+            }
+        }
         e->used += r->bytes;
         r->admitted = true;
         it = e->waiting.erase(it);
@@ -117,6 +206,7 @@ static void destroy_request(xc_engine* e, Request* r) {
         xc_context_destroy(r->ctx);
         r->ctx = nullptr;
     }
+    dev_release(r->phi_store);
     if (r->admitted) e->used -= std::min(e->used, r->bytes);
     r->admitted = false;
 }
@@ -127,6 +217,7 @@ struct Group {
     std::vector<ReqDev> rd;
     std::map<Integration*, int> slot;
     int gemm = 0, syr = 0;
+    bool sph = false;   // some request of the group has spherical shells
 };
 
 static int engine_step(xc_engine* e, int* launched) {
@@ -171,21 +262,34 @@ static int engine_step(xc_engine* e, int* launched) {
             xc_context* c = r->ctx;
             if (in->next_batch >= c->n_batches) continue;
             WaveBatch w = c->h_wb[in->next_batch];
-            const size_t bytes = batch_scratch_bytes(w);
+            const size_t bytes = r->cache ? batch_zpart_bytes(w) : batch_scratch_bytes(w);
             if (used + bytes > e->wave_bytes) continue;
             const int key = r->precision * 2 + (r->functional == XC_GGA_PBE ? 1 : 0);
             Group& g = groups[key];
+            g.sph = g.sph || c->any_pure;
             auto sl = g.slot.find(in);
             int req_slot;
             if (sl == g.slot.end()) {
                 req_slot = (int)g.rd.size();
                 g.slot[in] = req_slot;
-                g.rd.push_back(make_req(c, in->P, in->V));
+                ReqDev rd = make_req(c, in->P, in->V);
+                rd.phi_base = r->cache ? (char*)r->phi_store.p : nullptr;
+                g.rd.push_back(rd);
             } else {
                 req_slot = sl->second;
             }
-            w.phi_off = (long long)(used / 8);
-            w.part_off = (long long)(used / 8 + kSlabs * (size_t)w.nbp * w.ngp);
+            const long long slab = (long long)w.nbp * w.ngp;
+            if (r->cache) {
+                w.phi_off = r->phi_offs[in->next_batch];
+                w.z_off = (long long)(used / 8);
+                w.flags = r->phi_ready ? kSkipColloc : 0;
+            } else {
+                w.phi_off = (long long)(used / 8);
+                w.z_off = w.phi_off + (long long)(batch_phi_bytes(w) / 8);
+                w.flags = 0;
+            }
+            w.part_off = w.z_off + slab;
+            if (!(w.flags & kSkipColloc)) e->colloc_batches += 1;
             w.req = req_slot;
             used += bytes;
             const int gt = w.nmt * (w.ngp / kTile);
@@ -250,7 +354,7 @@ static int engine_step(xc_engine* e, int* launched) {
                                (const int*)e->d_gpre.p + o.pre,
                                (const int*)e->d_spre.p + o.pre, (int)g.wb.size(), g.gemm,
                                g.syr, (const ReqDev*)e->d_reqs.p, (char*)e->scratch.p,
-                               (int*)e->d_tmap.p));
+                               (int*)e->d_tmap.p, true, g.sph));
         }
         e->batches_launched += *launched;
     }
@@ -265,6 +369,9 @@ static int engine_step(xc_engine* e, int* launched) {
         XC_HIP(hipEventRecord(in->done, e->stream));
         in->launched_finish = true;
         r->active = nullptr;
+        // every batch's Phi is in the store now (later launches are ordered
+        // after these on the stream)
+        if (r->cache) r->phi_ready = true;
     }
     e->steps += 1;
     return XC_OK;
@@ -291,10 +398,31 @@ int xc_engine_create(const xc_engine_opts* opts, xc_engine** out) {
     e->wave_bytes = (opts && opts->wave_bytes) ? opts->wave_bytes
                                                : std::min<size_t>(fr / 8, (size_t)8 << 30);
     e->budget = (opts && opts->hbm_budget) ? opts->hbm_budget : fr / 2;
+    e->cache_phi = opts && opts->cache_phi;
+    st = hipGetDevice(&e->device);
+    if (st != hipSuccess) {
+        delete e;
+        return hip_fail(st, "hipGetDevice");
+    }
     int rc = dev_reserve(e->scratch, e->wave_bytes);
     if (rc != XC_OK) {
         delete e;
         return rc;
+    }
+    // default priority, like every stream of the library
+    st = hipStreamCreateWithFlags(&e->build_stream, hipStreamNonBlocking);
+    if (st != hipSuccess) {
+        dev_release(e->scratch);
+        delete e;
+        return hip_fail(st, "hipStreamCreateWithFlags");
+    }
+    try {
+        e->builder = std::thread(builder_main, e);
+    } catch (...) {
+        (void)hipStreamDestroy(e->build_stream);
+        dev_release(e->scratch);
+        delete e;
+        return fail(XC_ERR_NOMEM, "could not start the grid builder thread");
     }
     *out = e;
     return XC_OK;
@@ -393,6 +521,15 @@ int xc_engine_release(xc_engine* e, long long req_id) {
     Request* r = it->second;
     if (r->active || !r->queued.empty())
         return fail(XC_ERR_STATE, "request still has integrations in flight");
+    // a grid being built is the builder thread's until it is done
+    if (r->building)
+        while (!r->built.load(std::memory_order_acquire)) std::this_thread::yield();
+    if (r->est_charged) {
+        e->used -= std::min(e->used, r->est_bytes);
+        r->est_charged = false;
+    }
+    e->waiting.erase(std::remove(e->waiting.begin(), e->waiting.end(), req_id),
+                     e->waiting.end());
     r->released = true;
     destroy_request(e, r);
     e->reqs.erase(it);
@@ -414,11 +551,21 @@ int xc_engine_stats(xc_engine* e, xc_engine_info* s) {
     s->steps = e->steps;
     s->batches_launched = e->batches_launched;
     s->completed = e->completed;
+    s->colloc_batches = e->colloc_batches;
+    for (auto& kv : e->reqs) s->phi_cached += kv.second->cache ? 1 : 0;
     return XC_OK;
 }
 
 int xc_engine_destroy(xc_engine* e) {
     if (!e) return XC_OK;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        e->stop = true;
+    }
+    e->cv.notify_all();
+    if (e->builder.joinable()) e->builder.join();
+    (void)hipStreamSynchronize(e->build_stream);
+    (void)hipStreamDestroy(e->build_stream);
     (void)hipStreamSynchronize(e->stream);
     for (auto& kv : e->tickets) {
         if (kv.second->done) (void)hipEventDestroy(kv.second->done);

@@ -40,12 +40,16 @@ class ServeRequest:
 
 
 class DeviceDensities:
-    """Seeded SCF-like densities made on the device: P_0 = 2 C C^T with C
-    (nbf x n_occ) standard normal / sqrt(nbf), P_k = P_0 + delta_k with
-    delta_k symmetric, standard normal, scaled to Frobenius norm `norm`."""
+    """Seeded SCF-like densities made on the device from an S-orthonormal
+    orbital set: C_raw ~ N(0, 1) (nbf x n_occ), C = C_raw (C_raw^T S C_raw)^-1/2,
+    P_0 = 2 C C^T (so tr(P_0 S) = 2 n_occ), P_k = P_0 + delta_k with delta_k
+    symmetric, standard normal, scaled to Frobenius norm `norm`. S is the
+    host overlap matrix of the request's basis. Input generation only (torch
+    on the device); the integrations themselves run in the library."""
 
-    def __init__(self, nbf, n_occ, n_iter, seed, norm=1e-3):
-        self.nbf, self.n_occ, self.n_iter, self.seed, self.norm = nbf, n_occ, n_iter, seed, norm
+    def __init__(self, S, n_occ, n_iter, seed, norm=1e-3):
+        self.S, self.n_occ, self.n_iter, self.seed, self.norm = S, n_occ, n_iter, seed, norm
+        self.nbf = S.shape[0]
         self._p0 = None
 
     def __len__(self):
@@ -61,8 +65,13 @@ class DeviceDensities:
         import torch
         if self._p0 is None:
             C = torch.randn(self.nbf, self.n_occ, generator=self._gen(0), device="cuda",
-                            dtype=torch.float64) / self.nbf ** 0.5
-            self._p0 = 2.0 * (C @ C.T)
+                            dtype=torch.float64)
+            S = torch.from_numpy(np.ascontiguousarray(self.S)).cuda()
+            M = C.T @ (S @ C)
+            ev, U = torch.linalg.eigh(0.5 * (M + M.T))
+            C = C @ ((U / torch.sqrt(ev)) @ U.T)
+            P0 = 2.0 * (C @ C.T)
+            self._p0 = (0.5 * (P0 + P0.T)).contiguous()
         d = torch.randn(self.nbf, self.nbf, generator=self._gen(k + 1), device="cuda",
                         dtype=torch.float64)
         d = 0.5 * (d + d.T)
@@ -79,11 +88,12 @@ class DeviceDensities:
 class XcEngine:
     """Thin owner of an engine handle and its torch buffers."""
 
-    def __init__(self, hbm_budget=0, wave_bytes=0, stream=None):
+    def __init__(self, hbm_budget=0, wave_bytes=0, stream=None, cache_phi=True):
         import torch
         self.torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.handle = B.xc_engine_create(self.stream.cuda_stream, hbm_budget, wave_bytes)
+        self.handle = B.xc_engine_create(self.stream.cuda_stream, hbm_budget, wave_bytes,
+                                         cache_phi)
 
     def add(self, r):
         rid, nbf = B.xc_engine_add_request(self.handle, r.coords, r.mk_alpha, r.basis,
@@ -112,11 +122,14 @@ class XcEngine:
             self.handle = None
 
 
-def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None):
+def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None, exclude=(),
+          cache_phi=True):
     """Run the request stream; returns a summary dict. keep_v(i) -> bool selects
-    requests whose V matrices are copied back (for accuracy checks)."""
+    requests whose V matrices are copied back (for accuracy checks); requests
+    whose index is in `exclude` are served like the others but left out of
+    the throughput and latency figures."""
     import torch
-    eng = XcEngine(hbm_budget, wave_bytes)
+    eng = XcEngine(hbm_budget, wave_bytes, cache_phi=cache_phi)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
     nxt = 0
     inflight = {}      # ticket -> (request index, submit time, P, V, EN)
@@ -161,8 +174,9 @@ def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None):
                 vv = V.cpu().numpy() if (keep_v is not None and keep_v(i)) else None
                 r.results.append((float(en[0]), float(en[1]), vv))
                 r.int_latency.append(te - ts)
-                n_done_int += 1
-                points_done += r.n_points_nominal
+                if i not in exclude:
+                    n_done_int += 1
+                    points_done += r.n_points_nominal
                 r.k += 1
                 if r.k < len(r.densities):
                     submit(i)
@@ -178,8 +192,9 @@ def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None):
         st = eng.stats()
     finally:
         eng.close()
-    lat = np.array([x for r in requests for x in r.int_latency])
-    req_lat = np.array([r.t_done - r.arrival for r in requests])
+    kept = [r for i, r in enumerate(requests) if i not in exclude]
+    lat = np.array([x for r in kept for x in r.int_latency])
+    req_lat = np.array([r.t_done - r.arrival for r in kept])
     return {
         "wall_s": wall,
         "integrations": n_done_int,

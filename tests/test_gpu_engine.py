@@ -83,3 +83,28 @@ def test_engine_mixed_precisions_and_oracle():
     say(f"  engine vs oracle: dE {E - Eo:.2e} dN {N - No:.2e} dV {np.abs(V - Vo).max():.2e}")
     assert abs(E - Eo) <= 1e-10 and abs(N - No) <= 1e-10
     assert np.abs(V - Vo).max() <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_engine_phi_cache_same_results_fewer_collocations(precision):
+    """Keeping each request's Phi across its integrations gives E_xc and N_e
+    bit for bit (V to the atomic-add order) and runs collocation only for a
+    request's first integration; without the cache every integration
+    collocates."""
+    from paper_2007_03143_amd.serving import serve
+    runs = {}
+    for cache in (False, True):
+        reqs = _requests(n=4, n_iter=3, precision=precision)
+        summary = serve(reqs, wave_bytes=8 << 20, keep_v=lambda i: True, cache_phi=cache)
+        runs[cache] = (reqs, summary["engine"])
+        say(f"case engine {precision} cache={cache}: colloc batches "
+            f"{summary['engine']['colloc_batches']}, launched "
+            f"{summary['engine']['batches_launched']}")
+    (r0, e0), (r1, e1) = runs[False], runs[True]
+    assert e0["colloc_batches"] == e0["batches_launched"]
+    # first integration of each request only: a third of the batches
+    assert e1["colloc_batches"] * 3 == e1["batches_launched"]
+    for a, b in zip(r0, r1):
+        for (E0, N0, V0), (E1, N1, V1) in zip(a.results, b.results):
+            assert E0 == E1 and N0 == N1
+            assert np.abs(V0 - V1).max() <= 1e-13 * np.abs(V0).max()

@@ -21,12 +21,15 @@ TOL_V = 1e-10
 
 
 def _check(w, functional, **kw):
-    say(f"case {w.name} {functional} " + str({k: (np.nonzero(v)[0].tolist() if k == 'atom_mask' else v) for k, v in kw.items()}))
+    say(f"case {w.name} {functional} " + str({k: (np.nonzero(v)[0].tolist() if k == 'atom_mask' else v) for k, v in kw.items() if k != "becke_radius"}))
     E, N, V, st = gpu_integrate(w, functional, **kw)
-    okw = {k: v for k, v in kw.items() if k in ("atom_mask", "screen_eta", "n_rad")}
+    okw = {k: v for k, v in kw.items()
+           if k in ("atom_mask", "screen_eta", "n_rad", "partition", "becke_radius")}
     Eo, No, Vo = oracle_integrate(w, functional, **okw)
     say(f"  E gpu {E!r} oracle {Eo!r} dE {E - Eo:.3e} dN {N - No:.3e} "
-        f"max dV {np.abs(V - Vo).max():.3e} batches {st['n_batches']}")
+        f"max dV {np.abs(V - Vo).max():.3e} batches {st['n_batches']} "
+        f"max n_b {st['max_nb']} (row tiles {(st['max_nb'] + 63) // 64})")
+    assert 0 < st["max_nb"] <= w.nbf
     assert abs(E - Eo) <= TOL_E
     assert abs(N - No) <= TOL_E
     assert np.abs(V - Vo).max() <= TOL_V
@@ -47,6 +50,22 @@ def test_f_shell_parity(functional):
     w = cfg_water(polarisation=True)
     assert 3 in set(w.basis.shell_L.tolist())
     _check(w, functional)
+
+
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_spherical_shell_parity(functional):
+    """Spherical shells (2L+1 real solid harmonics for the f shell on O and
+    the d shells; 41 functions): the collocation, the density epilogue and
+    the Z kernel form them from the Cartesian components; FP64 parity, and
+    split BF16 within the mixed-precision bound."""
+    from gpu_util import gpu_integrate_prec
+    w = cfg_water(polarisation=True, pure=True)
+    assert w.nbf == 41 and w.basis.any_pure
+    _check(w, functional)
+    Eo, No, Vo = oracle_integrate(w, functional)
+    E, N, V, _ = gpu_integrate_prec(w, functional, "bf16")
+    say(f"  bf16: dE {E - Eo:.3e} dN {N - No:.3e} max dV {np.abs(V - Vo).max():.3e}")
+    assert abs(E - Eo) <= 1e-6 and abs(N - No) <= 1e-6
 
 
 def test_water_no_truncation_parity():
@@ -412,3 +431,96 @@ def test_footprint_matches_the_built_plan():
     finally:
         one.close()
         each.close()
+
+
+@pytest.mark.parametrize("functional", ["lda", "pbe"])
+def test_becke_partition_sfg_parity(functional):
+    """Becke's size-adjusted partition on the SFG grid of Table 2 (175 x 974
+    per atom, 511,350 points for the water)."""
+    w = cfg_water(n_rad=175, n_ang=974)
+    E, N, V, st = _check(w, functional, partition="becke", becke_radius=w.becke_radius)
+    assert st["n_points_nominal"] == 3 * 175 * 974
+
+
+def test_becke_weights_match_oracle():
+    """Grid weights of an 8-water cluster with Becke's partition against the
+    oracle's, point by point, with and without the size adjustment."""
+    w = cfg_water_cluster(8, functional="pbe", n_rad=30, n_ang=110)
+    for radius in (w.becke_radius, None):
+        say(f"case becke weights cluster8 adjusted={radius is not None}")
+        ctx = _grid_ctx(w, partition="becke", becke_radius=radius)
+        try:
+            xyzw, idx = ctx.export_grid()
+        finally:
+            ctx.close()
+        pts, wq, par = oracle.molecular_grid(w.coords, w.mk_alpha, w.n_rad, w.ang)
+        wo = oracle.becke_weights(pts, wq, par, w.coords, radius)
+        full = np.zeros_like(wo)
+        full[idx] = xyzw[:, 3]
+        say(f"  kept {len(idx)} of {len(wo)}, max |dw|/w_q {np.max(np.abs(full - wo) / wq):.2e}")
+        assert np.all(np.abs(full - wo) <= 1e-13 * wq)
+
+
+def test_becke_cluster_parity():
+    w = cfg_water_cluster(8, functional="pbe", n_rad=30, n_ang=110)
+    _check(w, "pbe", partition="becke", becke_radius=w.becke_radius)
+
+
+def test_functional_edge_cases_parity():
+    """The functional kernel's threshold, large reduced gradient and small
+    sigma branches against the oracle: an indefinite density (P_0 - 0.2 I,
+    so rho < 0 wherever the basis functions' squares outweigh rho_0) on a
+    fragment of the chain with its diffuse shells (long tails, large s)."""
+    from workloads import cfg_chain
+    w = cfg_chain(n_atoms=9, n_rad=40, n_ang=110)
+    P = w.P - 0.2 * np.eye(w.nbf)
+    Eo, No, Vo, det = oracle.integrate(w.coords, w.mk_alpha, w.basis, P, "pbe", w.n_rad,
+                                       w.ang, details=True)
+    rho, sig = det["rho"], det["sigma"]
+    pos = rho > 1e-15
+    kf = (3 * np.pi ** 2 * np.abs(rho[pos])) ** (1 / 3)
+    s_red = np.sqrt(sig[pos]) / (2 * kf * rho[pos])
+    n_neg, n_big_s = int((rho < 0).sum()), int((s_red > 10).sum())
+    n_small_sig = int((sig[pos] < 1e-20).sum())
+    say(f"case functional edges: {n_neg} points with rho < 0, {n_big_s} with s > 10, "
+        f"{n_small_sig} with sigma < 1e-20, of {rho.size}")
+    assert n_neg > 500 and n_big_s > 100 and n_small_sig > 100
+    for functional in ("lda", "pbe"):
+        E, N, V, st = gpu_integrate(w, functional, P=P)
+        if functional == "lda":
+            Eo, No, Vo = oracle.integrate(w.coords, w.mk_alpha, w.basis, P, "lda", w.n_rad,
+                                          w.ang)
+        say(f"  {functional}: dE {E - Eo:.3e} dN {N - No:.3e} max dV {np.abs(V - Vo).max():.3e}")
+        assert abs(E - Eo) <= TOL_E and abs(N - No) <= TOL_E
+        assert np.abs(V - Vo).max() <= TOL_V
+
+
+def test_chain600_full_grid_atoms_match_golden():
+    """The 600-atom chain at its full grid (99 x 590 per atom, the partition
+    over all 600 atoms, 6280 functions) against stored oracle values for a C
+    and an H parent atom (tests/golden/chain600_atoms.json, written by
+    make_chain600_golden.py from the oracle alone): E_xc and N_e, V on a
+    seeded sample of entries and every row sum of V, all to 1e-10. Both atoms
+    reach screened function counts above 2048 (more than 32 row tiles)."""
+    import json
+    import os
+    from workloads import cfg_chain
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "chain600_atoms.json")))
+    w = cfg_chain()
+    assert (w.n_rad, w.n_ang, w.nbf) == (gold["n_rad"], gold["n_ang"], gold["nbf"])
+    for g in gold["atoms"]:
+        mask = np.zeros(w.natoms, np.uint8)
+        mask[g["atom"]] = 1
+        say(f"case chain600 full grid atom {g['atom']} (Z {g['Z']})")
+        E, N, V, st = gpu_integrate(w, "pbe", atom_mask=mask)
+        r, c = np.array(g["sample_rows"]), np.array(g["sample_cols"])
+        dv = np.abs(V[r, c] - np.array(g["sample_values"])).max()
+        drs = np.abs(V.sum(axis=1) - np.array(g["row_sums"])).max()
+        say(f"  dE {E - g['E_xc']:.3e} dN {N - g['N_e']:.3e} sampled max dV {dv:.3e} "
+            f"({len(r)} entries) max d(row sum) {drs:.3e}; batches {st['n_batches']} "
+            f"max n_b {st['max_nb']} (row tiles {(st['max_nb'] + 63) // 64})")
+        assert st["max_nb"] > 2048
+        assert abs(E - g["E_xc"]) <= TOL_E and abs(N - g["N_e"]) <= TOL_E
+        assert dv <= TOL_V and drs <= TOL_V
+        assert np.array_equal(V, V.T)

@@ -474,7 +474,7 @@ def test_functional_edge_cases_parity():
     from workloads import cfg_chain
     w = cfg_chain(n_atoms=9, n_rad=40, n_ang=110)
     P = w.P - 0.2 * np.eye(w.nbf)
-    Eo, No, Vo, det = oracle.integrate(w.coords, w.mk_alpha, w.basis, P, "pbe", w.n_rad,
+    Ep, Np, Vp, det = oracle.integrate(w.coords, w.mk_alpha, w.basis, P, "pbe", w.n_rad,
                                        w.ang, details=True)
     rho, sig = det["rho"], det["sigma"]
     pos = rho > 1e-15
@@ -490,6 +490,8 @@ def test_functional_edge_cases_parity():
         if functional == "lda":
             Eo, No, Vo = oracle.integrate(w.coords, w.mk_alpha, w.basis, P, "lda", w.n_rad,
                                           w.ang)
+        else:
+            Eo, No, Vo = Ep, Np, Vp
         say(f"  {functional}: dE {E - Eo:.3e} dN {N - No:.3e} max dV {np.abs(V - Vo).max():.3e}")
         assert abs(E - Eo) <= TOL_E and abs(N - No) <= TOL_E
         assert np.abs(V - Vo).max() <= TOL_V

@@ -266,6 +266,29 @@ int xc_context_integrate(xc_context* ctx, int functional, int precision,
                          const double* d_P, double* d_V, double* d_EN);
 
 /*
+ * Spin-unrestricted integration (the extension Sec. 2.1 notes needs only a
+ * few more intermediates): two density matrices P^a, P^b (nbf x nbf FP64,
+ * device) give rho_a, rho_b, sigma_aa, sigma_ab, sigma_bb and
+ *   E_xc = sum_i w_i e(rho_a, rho_b, sigma_aa, sigma_ab, sigma_bb)
+ *   V^a = sum_i w_i [ v_rho_a phi phi^T + (2 v_sigma_aa grad rho_a
+ *         + v_sigma_ab grad rho_b) . (phi grad phi^T + grad phi phi^T) ]
+ * and V^b likewise (both written in full, exactly symmetric); d_EN receives
+ * E_xc and N_e (both spins). Functionals: Slater exchange by spin scaling +
+ * VWN5 with its spin interpolation (XC_LDA_SVWN5); PBE by spin scaling +
+ * PBE correlation on the spin-interpolated PW92 (XC_GGA_PBE). A point adds
+ * nothing when rho_a + rho_b < rho_thresh, a spin's exchange nothing when
+ * its density is below rho_thresh, and zeta = (rho_a - rho_b)/rho is held
+ * within [-1 + 1e-10, 1 - 1e-10]. Precision: XC_FP64 only
+ * (XC_ERR_UNSUPPORTED otherwise). The first such call re-plans the waves of
+ * the context with room for a second set of density partials (allocates);
+ * later calls, and XC_FP64 restricted integrations, use that plan.
+ * Stream-ordered like xc_context_integrate.
+ */
+int xc_context_integrate_uks(xc_context* ctx, int functional, int precision,
+                             const double* d_Pa, const double* d_Pb, double* d_Va,
+                             double* d_Vb, double* d_EN);
+
+/*
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc. The same
  * integration as xc_context_integrate (same kernels, same arguments and

@@ -7,6 +7,7 @@ from .binding import (XcContext, XcError, xc_abi_version, xc_context_build_grid,
                       xc_context_create, xc_context_destroy,
                       xc_context_export_batches, xc_context_export_grid,
                       xc_context_integrate, xc_context_integrate_noalloc,
+                      xc_context_integrate_uks,
                       xc_context_stats, xc_integrate, STATIC_SCRATCH_BYTES,
                       xc_context_set_timing, xc_context_set_phi_cache,
                       xc_context_footprint,
@@ -21,7 +22,7 @@ from .binding import (XcContext, XcError, xc_abi_version, xc_context_build_grid,
 __all__ = ["XcContext", "XcError", "xc_abi_version", "xc_context_build_grid",
            "xc_context_create", "xc_context_destroy", "xc_context_export_batches",
            "xc_context_export_grid", "xc_context_integrate",
-           "xc_context_integrate_noalloc", "STATIC_SCRATCH_BYTES", "xc_context_stats",
+           "xc_context_integrate_noalloc", "xc_context_integrate_uks", "STATIC_SCRATCH_BYTES", "xc_context_stats",
            "xc_integrate", "xc_strerror", "LIB_PATH", "xc_context_set_timing",
            "xc_context_set_phi_cache", "xc_context_footprint",
            "xc_context_timing", "PHASES", "xc_engine_create", "xc_engine_add_request",

@@ -141,6 +141,9 @@ def _load():
     lib.xc_context_integrate.restype = c_int
     lib.xc_context_integrate.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p,
                                          c_void_p]
+    lib.xc_context_integrate_uks.restype = c_int
+    lib.xc_context_integrate_uks.argtypes = [c_void_p, c_int, c_int, c_void_p, c_void_p,
+                                             c_void_p, c_void_p, c_void_p]
     lib.xc_context_integrate_noalloc.restype = c_int
     lib.xc_context_integrate_noalloc.argtypes = [c_void_p, c_int, c_int, c_void_p,
                                                  c_void_p, c_void_p]
@@ -283,6 +286,14 @@ def xc_context_integrate(handle, functional, precision, d_P, d_V, d_EN):
                                     c_void_p(d_V), c_void_p(d_EN)))
 
 
+def xc_context_integrate_uks(handle, functional, precision, d_Pa, d_Pb, d_Va, d_Vb, d_EN):
+    """Spin-unrestricted integration; device pointers (ints)."""
+    _check(LIB.xc_context_integrate_uks(handle, _code(FUNCTIONALS, functional),
+                                        _code(PRECISIONS, precision), c_void_p(d_Pa),
+                                        c_void_p(d_Pb), c_void_p(d_Va), c_void_p(d_Vb),
+                                        c_void_p(d_EN)))
+
+
 def xc_context_integrate_noalloc(handle, functional, precision, d_P, d_V, d_EN):
     """xc_context_integrate with the scratch in the library's static device
     array (no allocation); device pointers (ints)."""
@@ -423,6 +434,19 @@ class XcContext:
         xc_context_integrate(self.handle, functional, precision, P.data_ptr(),
                              self.V.data_ptr(), self.EN.data_ptr())
         return self.V, self.EN
+
+    def integrate_uks(self, Pa, Pb, functional, precision="fp64"):
+        """Spin-unrestricted: Pa, Pb (nbf, nbf) float64 cuda tensors. Returns
+        (Va, Vb, EN) device tensors, valid once the stream reaches here."""
+        for P in (Pa, Pb):
+            assert P.dtype == self.torch.float64 and P.is_cuda and P.is_contiguous()
+            assert tuple(P.shape) == (self.nbf, self.nbf)
+        if not hasattr(self, "Vb"):
+            self.Vb = self.torch.empty_like(self.V)
+        xc_context_integrate_uks(self.handle, functional, precision, Pa.data_ptr(),
+                                 Pb.data_ptr(), self.V.data_ptr(), self.Vb.data_ptr(),
+                                 self.EN.data_ptr())
+        return self.V, self.Vb, self.EN
 
     def stats(self):
         return xc_context_stats(self.handle)

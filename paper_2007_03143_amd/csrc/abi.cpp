@@ -124,7 +124,7 @@ size_t device_bytes(const xc_context* c) {
                             &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch,
-                            &c->epart, &c->npart, &c->d_req, &c->pdig, &c->pscale};
+                            &c->epart, &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta};
     size_t n = 0;
     for (const DevBuf* b : bufs) n += b->cap;
     return n;
@@ -236,7 +236,7 @@ static void release_all(xc_context* c) {
                       &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                       &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                       &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch, &c->epart,
-                      &c->npart, &c->d_req, &c->pdig, &c->pscale};
+                      &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta};
     for (DevBuf* b : bufs) dev_release(*b);
 }
 
@@ -287,7 +287,7 @@ static int plan_waves(xc_context* c) {
         w.nbp = nbp;
         w.ngp = ngp;
         w.nmt = nmt;
-        const size_t bytes = batch_scratch_bytes(w);
+        const size_t bytes = batch_scratch_bytes(w) + (c->spin_plan ? batch_spin_bytes(w) : 0);
         if (cur.count > 0 && used + bytes > budget) close_wave();
         w.phi_off = (long long)(used / 8);
         w.z_off = w.phi_off + (long long)(batch_phi_bytes(w) / 8);
@@ -319,13 +319,24 @@ static int plan_waves(xc_context* c) {
     close_wave();
     XC_TRY(upload(c->d_wb, c->h_wb.data(), sizeof(WaveBatch) * std::max<size_t>(1, c->h_wb.size()),
                   c->stream));
+    if (c->spin_plan) {
+        // the same batches with the beta partials (after the alpha ones) and
+        // the second request descriptor (P^b, V^b)
+        c->h_wb_beta = c->h_wb;
+        for (WaveBatch& w : c->h_wb_beta) {
+            w.part_off += (long long)(batch_spin_bytes(w) / 8);
+            w.req = 1;
+        }
+        XC_TRY(upload(c->d_wb_beta, c->h_wb_beta.data(),
+                      sizeof(WaveBatch) * std::max<size_t>(1, c->h_wb_beta.size()), c->stream));
+    }
     XC_TRY(upload(c->d_gemm_pre, gpre.data(), sizeof(int) * gpre.size(), c->stream));
     XC_TRY(upload(c->d_syr_pre, spre.data(), sizeof(int) * spre.size(), c->stream));
     int max_tiles = 1;
     for (const Wave& w : c->waves) max_tiles = std::max({max_tiles, w.gemm_tiles, w.syr_tiles});
     c->max_tiles = max_tiles;
     XC_TRY(dev_reserve(c->d_tmap, 2 * sizeof(int) * (size_t)max_tiles));
-    XC_TRY(dev_reserve(c->d_req, sizeof(ReqDev)));
+    XC_TRY(dev_reserve(c->d_req, (c->spin_plan ? 2 : 1) * sizeof(ReqDev)));
     if (!c->external_scratch)
         XC_TRY(dev_reserve(c->scratch, std::max<size_t>(c->max_wave_bytes, 8)));
     XC_TRY(dev_reserve(c->epart, 8 * (size_t)std::max<long long>(1, c->n_batches)));
@@ -508,6 +519,22 @@ int xc_context_integrate(xc_context* c, int functional, int precision, const dou
     XC_TRY(check_func_prec(functional, precision));
     if (!c->built) XC_TRY(build_grid(c));
     return run_integrate(c, functional, precision, dP, dV, dEN);
+}
+
+int xc_context_integrate_uks(xc_context* c, int functional, int precision, const double* dPa,
+                             const double* dPb, double* dVa, double* dVb, double* dEN) {
+    g_last_error.clear();
+    if (!c) return fail(XC_ERR_INVALID_ARG, "null context");
+    if (!dPa || !dPb || !dVa || !dVb || !dEN) return fail(XC_ERR_INVALID_ARG, "null device buffer");
+    XC_TRY(check_func_prec(functional, precision));
+    if (precision != XC_FP64)
+        return fail(XC_ERR_UNSUPPORTED, "spin-unrestricted integrations run in FP64 only");
+    if (!c->built) XC_TRY(build_grid(c));
+    if (!c->spin_plan) {
+        c->spin_plan = true;
+        XC_TRY(plan_waves(c));
+    }
+    return run_integrate_uks(c, functional, dPa, dPb, dVa, dVb, dEN);
 }
 
 int xc_context_integrate_noalloc(xc_context* c, int functional, int precision,

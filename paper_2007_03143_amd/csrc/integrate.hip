@@ -842,6 +842,82 @@ __global__ __launch_bounds__(256) void k_func(const WaveBatch* __restrict__ wb,
     }
 }
 
+// Spin-unrestricted functional: one workgroup per batch, one thread per
+// point. rho_s and grad rho_s from the alpha and the beta partials, the
+// spin-polarised functional, the batch's E_xc and N_e partials, and each
+// spin's Z factors a_s = w v_rho_s / 2 and
+// b_a = w (2 v_sigma_aa grad rho_a + v_sigma_ab grad rho_b) (b_b likewise),
+// written over the first row tile of that spin's partials.
+template <bool GGA>
+__global__ __launch_bounds__(256) void k_func_spin(const WaveBatch* __restrict__ wb,
+                                                   const ReqDev* __restrict__ reqs,
+                                                   char* __restrict__ scratch) {
+    const WaveBatch B = wb[blockIdx.x];
+    const ReqG R = global_view(reqs[B.req]);
+    const gptr<const double> W = R.pw;
+    const double thr = R.rho_thresh;
+    __shared__ double red[256];
+    double* pa = (double*)(scratch + 8 * B.part_off);
+    double* pb = pa + (size_t)B.nmt * 4 * B.ngp;
+    double eacc = 0.0, nacc = 0.0;
+    for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
+        double fa[4] = {0.0, 0.0, 0.0, 0.0}, fb[4] = {0.0, 0.0, 0.0, 0.0};
+        if (i < B.ng) {
+            double ra = 0.0, rb = 0.0, ga[3] = {0.0, 0.0, 0.0}, gb[3] = {0.0, 0.0, 0.0};
+            for (int mt = 0; mt < B.nmt; ++mt) {
+                const size_t o = (size_t)mt * 4 * B.ngp + i;
+                ra += pa[o];
+                rb += pb[o];
+                if (GGA) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        ga[d] += pa[o + (size_t)(d + 1) * B.ngp];
+                        gb[d] += pb[o + (size_t)(d + 1) * B.ngp];
+                    }
+                }
+            }
+            const double w = W[B.pt_off + i];
+            nacc += w * (ra + rb);
+            if (ra + rb >= thr) {
+                double e, va, vb;
+                if (GGA) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        ga[d] *= 2.0;
+                        gb[d] *= 2.0;
+                    }
+                    const double saa = ga[0] * ga[0] + ga[1] * ga[1] + ga[2] * ga[2];
+                    const double sab = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                    const double sbb = gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2];
+                    double vsaa, vsab, vsbb;
+                    fn::gga_pbe_spin(ra, rb, saa, sab, sbb, thr, e, va, vb, vsaa, vsab, vsbb);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        fa[d + 1] = w * (2.0 * vsaa * ga[d] + vsab * gb[d]);
+                        fb[d + 1] = w * (2.0 * vsbb * gb[d] + vsab * ga[d]);
+                    }
+                } else {
+                    fn::lda_svwn5_spin(ra, rb, thr, e, va, vb);
+                }
+                eacc += w * e;
+                fa[0] = 0.5 * w * va;
+                fb[0] = 0.5 * w * vb;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pa[(size_t)q * B.ngp + i] = fa[q];
+            pb[(size_t)q * B.ngp + i] = fb[q];
+        }
+    }
+    const double es = block_sum_256(eacc, red);
+    const double ns = block_sum_256(nacc, red);
+    if (threadIdx.x == 0) {
+        R.epart[B.batch] = es;
+        R.npart[B.batch] = ns;
+    }
+}
+
 // Z^j (eq. z_mat), stored in slab 1: z = a phi + b . grad phi with phi and
 // grad phi re-evaluated from the shell data. One workgroup per batch; each
 // lane takes a point (its coordinates and Z factors read once), the wave
@@ -1110,6 +1186,7 @@ __global__ __launch_bounds__(256) void k_syr2k(
 // in LDS with a row pitch of 40 bf16, so that the 16-byte fragment reads of
 // 16 lanes fall in distinct banks.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int kKB = 32;        // K step of the split-BF16 kernels
 constexpr int kBP = kKB + 8;   // LDS row pitch in bf16
 
@@ -1178,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_p_digits(const double* __restrict__ P, 
 // Same tiles and epilogue as k_gemm_rho; one LDS buffer (eight digit planes,
 // 40 KB) with the next step's loads in registers.
 template <bool GGA>
-__global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
+__global__ __launch_bounds__(256, 3) void k_gemm_rho_bf16(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
     const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
     const int t = xcd_remap(blockIdx.x, ntiles);
@@ -1286,96 +1363,81 @@ __global__ __launch_bounds__(256, 2) void k_gemm_rho_bf16(
         for (int u = 0; u < 4; ++u) *reinterpret_cast<bf16x8*>(&plane(4 + u)[bn][bk]) = d[u];
     };
 
-    v4f acc[4][2][2];
-    v4d acc64[2][2];
-    bool live[2][2];
+    // each wave: one 32 x 32 block (v_mfma_f32_32x32x16_bf16; operand lane l
+    // holds A[l % 32][8 (l / 32) + t] and B[8 (l / 32) + t][l % 32], and
+    // accumulator register r of lane l holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32])
+    v16f acc[4];
+    double acc64[16];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
+        for (int r = 0; r < 16; ++r) acc[g][r] = 0.f;
 #pragma unroll
-            for (int g = 0; g < 4; ++g) acc[g][mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
-            acc64[mb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
-            live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + wn * 32 + nb * 16 < B.ng);
-        }
+    for (int r = 0; r < 16; ++r) acc64[r] = 0.0;
+    const bool live = (m0 + wm * 32 < B.nb) && (n0 + wn * 32 < B.ng);
     auto flush = [&]() {
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int r = 0; r < 16; ++r) {
+            double v = (double)acc[3][r];
+            v = fma(v, 0x1p-8, (double)acc[2][r]);
+            v = fma(v, 0x1p-8, (double)acc[1][r]);
+            v = fma(v, 0x1p-8, (double)acc[0][r]);
+            acc64[r] += v;
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    double v = (double)acc[3][mb][nb][r];
-                    v = fma(v, 0x1p-8, (double)acc[2][mb][nb][r]);
-                    v = fma(v, 0x1p-8, (double)acc[1][mb][nb][r]);
-                    v = fma(v, 0x1p-8, (double)acc[0][mb][nb][r]);
-                    acc64[mb][nb][r] += v;
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) acc[g][mb][nb][r] = 0.f;
-                }
+            for (int g = 0; g < 4; ++g) acc[g][r] = 0.f;
+        }
     };
 
-    gload(0);
-    sstore(0);
+    // per step: load, stage into LDS, compute (no operands carried across the
+    // MFMAs in registers: three workgroups per CU hide each other's loads)
     if (nk > 2) fetch(2);
-    __syncthreads();
-    const int fk = 8 * (lane >> 4);
+    const int ar32 = lane & 31, fk = 8 * (lane >> 5);
     for (int ks = 0; ks < nk; ++ks) {
-        if (ks + 1 < nk) gload(ks + 1);
-        bf16x8 b[4][2];
+        gload(ks);
+        sstore(ks);
+        __syncthreads();
+        // every thread has read this step's index slot: refill it with step ks + 2
+        if (ks + 2 < nk) {
+            fput(ks & 1);
+            if (ks + 3 < nk) fetch(ks + 3);
+        }
+        if (live) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int h = 0; h < 2; ++h) {
+                bf16x8 a[4], b[4];
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-                b[u][nb] = *reinterpret_cast<const bf16x8*>(
-                    &plane(4 + u)[wn * 32 + nb * 16 + (lane & 15)][fk]);
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            bf16x8 a[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                a[u] = *reinterpret_cast<const bf16x8*>(
-                    &plane(u)[wm * 32 + mb * 16 + (lane & 15)][fk]);
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                if (!live[mb][nb]) continue;
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = *reinterpret_cast<const bf16x8*>(
+                        &plane(u)[wm * 32 + ar32][h * 16 + fk]);
+                    b[u] = *reinterpret_cast<const bf16x8*>(
+                        &plane(4 + u)[wn * 32 + ar32][h * 16 + fk]);
+                }
 #pragma unroll
                 for (int g = 0; g < 4; ++g)
 #pragma unroll
                     for (int u = 0; u <= g; ++u)
-                        acc[g][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            a[u], b[g - u][nb], acc[g][mb][nb], 0, 0, 0);
+                        acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b[g - u], acc[g],
+                                                                         0, 0, 0);
             }
         }
         if ((ks & 7) == 7) flush();
         __syncthreads();
-        if (ks + 1 < nk) {
-            sstore(ks + 1);
-            if (ks + 2 < nk) {
-                fput(ks & 1);
-                if (ks + 3 < nk) fetch(ks + 3);
-            }
-            __syncthreads();
-        }
     }
     flush();
 
     // X = acc64 2^{-14} s_mu s_i (the loop ended on a barrier, so the operand
     // planes are free for the X tile)
+    {
+        const int tc = wn * 32 + ar32;
+        const double sn = pscale[n0 + tc] * 0x1p-14;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            const int tc = wn * 32 + nb * 16 + (lane & 15);
-            const double sn = pscale[n0 + tc] * 0x1p-14;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int tr = wm * 32 + mb * 16 + 4 * (lane >> 4) + r;
-                const int f = frow[tr];
-                const double sm = f >= 0 ? R.Pscale[f] : 0.0;
-                Xs[tr][tc] = acc64[mb][nb][r] * sm * sn;
-            }
+        for (int r = 0; r < 16; ++r) {
+            const int tr = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int f = frow[tr];
+            const double sm = f >= 0 ? R.Pscale[f] : 0.0;
+            Xs[tr][tc] = acc64[r] * sm * sn;
         }
+    }
     __syncthreads();
     rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, frow, ex, ey, ez, has, scratch);
 }
@@ -1718,6 +1780,75 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
     return gga ? launch_wave_t<true, double, double>(XC_WAVE_ARGS)
                : launch_wave_t<false, double, double>(XC_WAVE_ARGS);
 #undef XC_WAVE_ARGS
+}
+
+// Spin-unrestricted wave (FP64): collocation once, the density contraction
+// for each spin (d_wa: alpha batches with request 0, d_wb_b: the same
+// batches with the beta partials and request 1), the spin functional, then Z
+// and the potential contraction for each spin in turn (the Z slab is reused).
+template <bool GGA>
+static int launch_wave_uks_t(hipStream_t s, const WaveBatch* wa, const WaveBatch* wbb,
+                             const int* gpre, const int* spre, int count, int gemm_tiles,
+                             int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
+                             bool sph) {
+    hipLaunchKernelGGL((k_colloc<double, false>), dim3(count), dim3(256), 0, s, wa, reqs, scr);
+    XC_HIP(hipGetLastError());
+    if (gemm_tiles > 0) {
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, gpre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+        for (const WaveBatch* w : {wa, wbb}) {
+            hipLaunchKernelGGL((k_gemm_rho<GGA, double>), dim3(gemm_tiles), dim3(256), 0, s, w,
+                               (const int2*)tmap, gemm_tiles, reqs, scr);
+            XC_HIP(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL((k_func_spin<GGA>), dim3(count), dim3(256), 0, s, wa, reqs, scr);
+    XC_HIP(hipGetLastError());
+    if (syr_tiles > 0) {
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, spre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+    }
+    for (const WaveBatch* w : {wa, wbb}) {
+        if (sph) hipLaunchKernelGGL((k_z<double, true>), dim3(count), dim3(256), 0, s, w, reqs, scr);
+        else hipLaunchKernelGGL((k_z<double, false>), dim3(count), dim3(256), 0, s, w, reqs, scr);
+        XC_HIP(hipGetLastError());
+        if (syr_tiles > 0) {
+            hipLaunchKernelGGL((k_syr2k<double, double>), dim3(syr_tiles), dim3(256), 0, s, w,
+                               (const int2*)tmap, syr_tiles, reqs, (const char*)scr);
+            XC_HIP(hipGetLastError());
+        }
+    }
+    return XC_OK;
+}
+
+int run_integrate_uks(xc_context* c, int functional, const double* dPa, const double* dPb,
+                      double* dVa, double* dVb, double* dEN) {
+    const bool gga = functional == XC_GGA_PBE;
+    const long long nn = (long long)c->nbf * c->nbf;
+    XC_TRY(launch_fill(c->stream, dVa, nn, 0.0));
+    XC_TRY(launch_fill(c->stream, dVb, nn, 0.0));
+    XC_TRY(dev_reserve(c->d_req, 2 * sizeof(ReqDev)));
+    ReqDev* d_req = (ReqDev*)c->d_req.p;
+    XC_TRY(launch_put_req(c->stream, d_req, make_req(c, dPa, dVa)));
+    XC_TRY(launch_put_req(c->stream, d_req + 1, make_req(c, dPb, dVb)));
+    c->phi_cached_kind = 0;
+    const WaveBatch* wa = (const WaveBatch*)c->d_wb.p;
+    const WaveBatch* wbb = (const WaveBatch*)c->d_wb_beta.p;
+    const int* gpre = (const int*)c->d_gemm_pre.p;
+    const int* spre = (const int*)c->d_syr_pre.p;
+    for (const Wave& w : c->waves) {
+        if (w.count == 0) continue;
+        XC_TRY((gga ? launch_wave_uks_t<true> : launch_wave_uks_t<false>)(
+            c->stream, wa + w.wb_off, wbb + w.wb_off, gpre + w.pre_off, spre + w.pre_off, w.count,
+            w.gemm_tiles, w.syr_tiles, d_req, (char*)c->scratch.p, (int2*)c->d_tmap.p,
+            c->any_pure));
+    }
+    XC_TRY(launch_finish(nullptr, c->stream, dVb, c->nbf, (const double*)c->epart.p,
+                         (const double*)c->npart.p, c->n_batches, dEN));
+    return launch_finish(nullptr, c->stream, dVa, c->nbf, (const double*)c->epart.p,
+                         (const double*)c->npart.p, c->n_batches, dEN);
 }
 
 int phi_kind(int precision) {

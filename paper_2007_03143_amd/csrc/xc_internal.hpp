@@ -109,6 +109,12 @@ inline size_t batch_scratch_bytes(const WaveBatch& w) {
     return batch_phi_bytes(w) + batch_zpart_bytes(w);
 }
 
+// Extra wave-scratch bytes of one batch for spin-unrestricted integrations:
+// a second set of density partials (the beta spin's), after the first.
+inline size_t batch_spin_bytes(const WaveBatch& w) {
+    return 8 * (size_t)w.nmt * 4 * w.ngp;
+}
+
 // Offset (doubles, from the batch's Phi slab) of its per-point digit scales.
 __host__ __device__ inline long long scale_row_off(const WaveBatch& w) {
     return (long long)w.nbp * w.ngp;
@@ -225,6 +231,9 @@ struct xc_context {
     xc::DevBuf scratch;
     size_t max_wave_bytes = 0;
     int max_tiles = 1;           // most tiles of one contraction launch in any wave
+    bool spin_plan = false;      // batches carry a second (beta) set of partials
+    std::vector<xc::WaveBatch> h_wb_beta;
+    xc::DevBuf d_wb_beta;        // the batches with the beta partials and request 1
     xc::DevBuf epart, npart;
     xc::DevBuf d_req;            // one ReqDev for the context's own integrations
     xc::DevBuf pdig, pscale;     // digits and row scales of P (split-BF16 mode)
@@ -298,6 +307,10 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre,
                 int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
                 char* scratch, int* d_tmap, bool colloc, bool sph);
+// Spin-unrestricted integration (FP64) of a context planned with
+// spin_plan: P^a, P^b in, V^a, V^b and (E_xc, N_e) out.
+int run_integrate_uks(xc_context* c, int functional, const double* dPa, const double* dPb,
+                      double* dVa, double* dVb, double* dEN);
 // noalloc.hip: the integration with its wave scratch, tile map and request
 // descriptor in the library's static device array (no allocation).
 int run_integrate_noalloc(xc_context* c, int functional, int precision, const double* dP,

@@ -403,7 +403,8 @@ def serving_run(n_req, s_pool_result, seed=5, load=0.7, n_sat=100, check_frac=0.
                             arrival=float(arrival), name=w.name, n_points_nominal=npts)
 
     n_sat = min(n_sat, n_req)
-    closed = serve([make(i, 0.0) for i in range(n_sat)], wave_bytes=2 << 30)
+    closed = serve([make(i, 0.0) for i in range(n_sat)], wave_bytes=2 << 30, log=log,
+                   log_every=25)
     saturation = closed["points_per_s"]
     log(f"  closed-loop on {n_sat} requests: {saturation / 1e6:.1f} Mpts/s")
     lam = load * saturation / mean_pts
@@ -440,7 +441,7 @@ def serving_run(n_req, s_pool_result, seed=5, load=0.7, n_sat=100, check_frac=0.
         twin_ids = set(range(n_req, n_req + len(twins)))
         summary = serve(reqs + twins, wave_bytes=2 << 30,
                         keep_v=lambda i: (i in twin_ids) or any(r == i for r, _ in checked_v),
-                        exclude=twin_ids)
+                        exclude=twin_ids, log=log, log_every=50)
         log(f"  served {summary['integrations']} integrations in {summary['wall_s']:.1f} s; "
             "waiting for the oracle checks")
         checks = []

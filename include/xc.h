@@ -52,6 +52,16 @@ extern "C" {
 /* exchange-correlation functionals (spin-unpolarised) */
 #define XC_LDA_SVWN5 1   /* Slater exchange + VWN5 correlation */
 #define XC_GGA_PBE   2   /* PBE exchange + PBE correlation (PW92 base) */
+#define XC_MGGA_TPSS 3   /* TPSS meta-GGA (Tao, Perdew, Staroverov, Scuseria 2003):
+                            e(rho, sigma, tau) with the kinetic energy density
+                            tau = 1/2 sum P_mn grad phi_m . grad phi_n, the extension
+                            Sec. 2.1 notes needs only a few more intermediates; V adds
+                            sum_i w_i v_tau grad phi_m . grad phi_n / 2. XC_FP64 only,
+                            spin-restricted only; z = tau_W/tau is held at 1 where
+                            tau < tau_W. The first such call on a context re-plans its
+                            waves with room for three gradient slabs and three more
+                            sets of partials per batch (allocates); not available
+                            through xc_context_integrate_noalloc or the engine. */
 
 /* arithmetic of the collocation and the two batched contractions */
 #define XC_FP64          0   /* everything FP64 */

@@ -25,6 +25,7 @@ XC_ERR_STATE = -5
 
 XC_LDA_SVWN5 = 1
 XC_GGA_PBE = 2
+XC_MGGA_TPSS = 3
 XC_FP64 = 0
 XC_MIXED_FP32 = 1
 XC_MIXED_BF16 = 2
@@ -34,7 +35,8 @@ XC_PARTITION_SSF = 0
 XC_PARTITION_BECKE = 1
 PARTITIONS = {"ssf": XC_PARTITION_SSF, "becke": XC_PARTITION_BECKE}
 
-FUNCTIONALS = {"lda": XC_LDA_SVWN5, "svwn5": XC_LDA_SVWN5, "pbe": XC_GGA_PBE}
+FUNCTIONALS = {"lda": XC_LDA_SVWN5, "svwn5": XC_LDA_SVWN5, "pbe": XC_GGA_PBE,
+               "tpss": XC_MGGA_TPSS}
 PRECISIONS = {"fp64": XC_FP64, "fp32": XC_MIXED_FP32, "bf16": XC_MIXED_BF16,
               "fp32v": XC_MIXED_FP32_V}
 

@@ -124,7 +124,8 @@ size_t device_bytes(const xc_context* c) {
                             &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                             &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch,
-                            &c->epart, &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta};
+                            &c->epart, &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta,
+                            &c->d_wb_meta};
     size_t n = 0;
     for (const DevBuf* b : bufs) n += b->cap;
     return n;
@@ -217,8 +218,10 @@ static int validate_inputs(const xc_molecule* mol, const xc_basis* basis,
 }
 
 static int check_func_prec(int functional, int precision) {
-    if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE)
+    if (functional != XC_LDA_SVWN5 && functional != XC_GGA_PBE && functional != XC_MGGA_TPSS)
         return fail(XC_ERR_UNSUPPORTED, "unknown functional");
+    if (functional == XC_MGGA_TPSS && precision != XC_FP64)
+        return fail(XC_ERR_UNSUPPORTED, "meta-GGA integrations run in FP64 only");
     if (precision != XC_FP64 && precision != XC_MIXED_FP32 && precision != XC_MIXED_FP32_V &&
         precision != XC_MIXED_BF16)
         return fail(XC_ERR_UNSUPPORTED, "precision not available");
@@ -236,7 +239,7 @@ static void release_all(xc_context* c) {
                       &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                       &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                       &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch, &c->epart,
-                      &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta};
+                      &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta, &c->d_wb_meta};
     for (DevBuf* b : bufs) dev_release(*b);
 }
 
@@ -287,7 +290,10 @@ static int plan_waves(xc_context* c) {
         w.nbp = nbp;
         w.ngp = ngp;
         w.nmt = nmt;
-        const size_t bytes = batch_scratch_bytes(w) + (c->spin_plan ? batch_spin_bytes(w) : 0);
+        // the spin and the meta-GGA extras share the room after the partials
+        const size_t bytes =
+            batch_scratch_bytes(w) + std::max(c->spin_plan ? batch_spin_bytes(w) : 0,
+                                              c->meta_plan ? batch_meta_bytes(w) : 0);
         if (cur.count > 0 && used + bytes > budget) close_wave();
         w.phi_off = (long long)(used / 8);
         w.z_off = w.phi_off + (long long)(batch_phi_bytes(w) / 8);
@@ -329,6 +335,21 @@ static int plan_waves(xc_context* c) {
         }
         XC_TRY(upload(c->d_wb_beta, c->h_wb_beta.data(),
                       sizeof(WaveBatch) * std::max<size_t>(1, c->h_wb_beta.size()), c->stream));
+    }
+    if (c->meta_plan) {
+        // three copies of the batches: gradient slab d in place of Phi,
+        // partial set d in place of the density partials
+        const size_t n = c->h_wb.size();
+        c->h_wb_meta.resize(3 * n);
+        for (int d = 0; d < 3; ++d)
+            for (size_t j = 0; j < n; ++j) {
+                WaveBatch w = c->h_wb[j];
+                w.phi_off = meta_grad_off(c->h_wb[j], d);
+                w.part_off = meta_part_off(c->h_wb[j], d);
+                c->h_wb_meta[d * n + j] = w;
+            }
+        XC_TRY(upload(c->d_wb_meta, c->h_wb_meta.data(),
+                      sizeof(WaveBatch) * std::max<size_t>(1, c->h_wb_meta.size()), c->stream));
     }
     XC_TRY(upload(c->d_gemm_pre, gpre.data(), sizeof(int) * gpre.size(), c->stream));
     XC_TRY(upload(c->d_syr_pre, spre.data(), sizeof(int) * spre.size(), c->stream));
@@ -518,6 +539,13 @@ int xc_context_integrate(xc_context* c, int functional, int precision, const dou
     if (!dP || !dV || !dEN) return fail(XC_ERR_INVALID_ARG, "null device buffer");
     XC_TRY(check_func_prec(functional, precision));
     if (!c->built) XC_TRY(build_grid(c));
+    if (functional == XC_MGGA_TPSS) {
+        if (!c->meta_plan) {
+            c->meta_plan = true;
+            XC_TRY(plan_waves(c));
+        }
+        return run_integrate_meta(c, dP, dV, dEN);
+    }
     return run_integrate(c, functional, precision, dP, dV, dEN);
 }
 
@@ -529,6 +557,8 @@ int xc_context_integrate_uks(xc_context* c, int functional, int precision, const
     XC_TRY(check_func_prec(functional, precision));
     if (precision != XC_FP64)
         return fail(XC_ERR_UNSUPPORTED, "spin-unrestricted integrations run in FP64 only");
+    if (functional == XC_MGGA_TPSS)
+        return fail(XC_ERR_UNSUPPORTED, "meta-GGA integrations are spin-restricted only");
     if (!c->built) XC_TRY(build_grid(c));
     if (!c->spin_plan) {
         c->spin_plan = true;
@@ -543,6 +573,8 @@ int xc_context_integrate_noalloc(xc_context* c, int functional, int precision,
     if (!c) return fail(XC_ERR_INVALID_ARG, "null context");
     if (!dP || !dV || !dEN) return fail(XC_ERR_INVALID_ARG, "null device buffer");
     XC_TRY(check_func_prec(functional, precision));
+    if (functional == XC_MGGA_TPSS)
+        return fail(XC_ERR_UNSUPPORTED, "meta-GGA integrations need the allocating entry point");
     if (!c->built) return fail(XC_ERR_STATE, "grid not built (building allocates device memory)");
     return run_integrate_noalloc(c, functional, precision, dP, dV, dEN);
 }
@@ -723,12 +755,16 @@ int xc_integrate(const xc_molecule* mol, const xc_basis* basis, const xc_grid_sp
     XC_TRY(xc_context_create(mol, basis, g, nullptr, &c));
     const size_t mb = 8 * (size_t)nbf * nbf;
     DevBuf dP, dV, dEN;
+    c->meta_plan = functional == XC_MGGA_TPSS;   // planned with the meta-GGA extras
     int rc = build_grid(c);
     if (rc == XC_OK) rc = upload(dP, P, mb, c->stream);
     if (rc == XC_OK) rc = dev_reserve(dV, mb);
     if (rc == XC_OK) rc = dev_reserve(dEN, 16);
-    if (rc == XC_OK) rc = run_integrate(c, functional, precision, (const double*)dP.p,
-                                        (double*)dV.p, (double*)dEN.p);
+    if (rc == XC_OK)
+        rc = functional == XC_MGGA_TPSS
+                 ? run_integrate_meta(c, (const double*)dP.p, (double*)dV.p, (double*)dEN.p)
+                 : run_integrate(c, functional, precision, (const double*)dP.p, (double*)dV.p,
+                                 (double*)dEN.p);
     double en[2] = {0.0, 0.0};
     std::vector<double> hv;
     if (rc == XC_OK) {

@@ -21,6 +21,7 @@
 
 #include "device_util.hpp"
 #include "functional.hpp"
+#include "functional_mgga.hpp"
 #include "xc_internal.hpp"
 
 
@@ -972,6 +973,133 @@ __global__ __launch_bounds__(256) void k_z(const WaveBatch* __restrict__ wb,
     }
 }
 
+// Gradient slabs of a meta-GGA batch: d phi/dx, d phi/dy, d phi/dz of its
+// screened functions at its points (rows and padding as in Phi), in the
+// three slabs after its partials. The walk of the Z kernel, with the Z
+// factors a = 0 and b = the unit vector of each direction.
+template <int L, bool PURE>
+__device__ inline void grad_shell3(double dx, double dy, double dz, double rad, double drad,
+                                   double* out, size_t slab, int ngp) {
+    z_shell<L, double, PURE>(dx, dy, dz, rad, drad, 0.0, 1.0, 0.0, 0.0, out, ngp);
+    z_shell<L, double, PURE>(dx, dy, dz, rad, drad, 0.0, 0.0, 1.0, 0.0, out + slab, ngp);
+    z_shell<L, double, PURE>(dx, dy, dz, rad, drad, 0.0, 0.0, 0.0, 1.0, out + 2 * slab, ngp);
+}
+
+template <bool SPH>
+__global__ __launch_bounds__(256) void k_grad(const WaveBatch* __restrict__ wb,
+                                              const ReqDev* __restrict__ reqs,
+                                              char* __restrict__ scratch) {
+    exp_table_init();
+    const WaveBatch B = wb[blockIdx.x];
+    const ReqG R = global_view(reqs[B.req]);
+    double* G = (double*)(scratch + 8 * meta_grad_off(B, 0));
+    const size_t slab = (size_t)B.nbp * B.ngp;
+    const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
+    for (int d = 0; d < 3; ++d)
+        for (long long k = threadIdx.x; k < npad; k += blockDim.x)
+            G[d * slab + (size_t)B.nb * B.ngp + k] = 0.0;
+    __syncthreads();  // the exponential table
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    for (int i = lane; i < B.ngp; i += 64) {
+        const bool hasp = i < B.ng;
+        double px = 0.0, py = 0.0, pz = 0.0;
+        if (hasp) {
+            px = R.px[B.pt_off + i];
+            py = R.py[B.pt_off + i];
+            pz = R.pz[B.pt_off + i];
+        }
+        for (int sl = wave; sl < B.nshell; sl += 4) {
+            const int sidx = R.shell_list[B.shell_off + sl];
+            const int loff = R.shell_loff[B.shell_off + sl];
+            const ShellDev sh = load_shell(R.shells + sidx);
+            double dx = 0.0, dy = 0.0, dz = 0.0, rad = 0.0, drad = 0.0;
+            if (hasp) {
+                const double r2 = dist2_nc(px, py, pz, sh, dx, dy, dz);
+                shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
+            }
+            double* out = G + (size_t)loff * B.ngp + i;
+            if (SPH && sh.pure) {
+                if (sh.L == 2) grad_shell3<2, SPH>(dx, dy, dz, rad, drad, out, slab, B.ngp);
+                else grad_shell3<3, SPH>(dx, dy, dz, rad, drad, out, slab, B.ngp);
+            } else {
+                switch (sh.L) {
+                    case 0: grad_shell3<0, false>(dx, dy, dz, rad, drad, out, slab, B.ngp); break;
+                    case 1: grad_shell3<1, false>(dx, dy, dz, rad, drad, out, slab, B.ngp); break;
+                    case 2: grad_shell3<2, false>(dx, dy, dz, rad, drad, out, slab, B.ngp); break;
+                    default: grad_shell3<3, false>(dx, dy, dz, rad, drad, out, slab, B.ngp); break;
+                }
+            }
+        }
+    }
+}
+
+// Meta-GGA functional (TPSS): one workgroup per batch, one thread per point.
+// rho and grad rho from the density partials; tau = 1/2 sum_d of row 1 + d
+// of partial set d (the contraction of P with d phi/dd, dotted with d phi/dd
+// in the density epilogue); E_xc and N_e partials. Writes the Z factors
+// a = w v_rho / 2, b = 2 w v_sigma grad rho over the first row tile of the
+// density partials and, over the first row tile of set d, the factors
+// (0, c e_d) with c = w v_tau / 4, so that the Z kernel run on set d forms
+// Z_d = c d phi/dd and the potential contraction with the d-th gradient
+// slab adds 2 c d phi/dd d phi/dd^T = w v_tau / 2 d phi/dd d phi/dd^T.
+__global__ __launch_bounds__(256) void k_func_meta(const WaveBatch* __restrict__ wb,
+                                                   const ReqDev* __restrict__ reqs,
+                                                   char* __restrict__ scratch) {
+    const WaveBatch B = wb[blockIdx.x];
+    const ReqG R = global_view(reqs[B.req]);
+    const gptr<const double> W = R.pw;
+    const double thr = R.rho_thresh;
+    __shared__ double red[256];
+    double* part = (double*)(scratch + 8 * B.part_off);
+    double* tp[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) tp[d] = (double*)(scratch + 8 * meta_part_off(B, d));
+    double eacc = 0.0, nacc = 0.0;
+    for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
+        double f[4] = {0.0, 0.0, 0.0, 0.0}, cf = 0.0;
+        if (i < B.ng) {
+            double rho = 0.0, g[3] = {0.0, 0.0, 0.0}, tau = 0.0;
+            for (int mt = 0; mt < B.nmt; ++mt) {
+                const size_t o = (size_t)mt * 4 * B.ngp + i;
+                rho += part[o];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    g[d] += part[o + (size_t)(d + 1) * B.ngp];
+                    tau += tp[d][o + (size_t)(d + 1) * B.ngp];
+                }
+            }
+            tau *= 0.5;
+            const double w = W[B.pt_off + i];
+            nacc += w * rho;
+            if (rho >= thr) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) g[d] *= 2.0;
+                const double sigma = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+                double e, vr, vs, vt;
+                mgga::tpss(rho, sigma, tau, e, vr, vs, vt);
+                eacc += w * e;
+                f[0] = 0.5 * w * vr;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) f[d + 1] = 2.0 * w * vs * g[d];
+                cf = 0.25 * w * vt;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[(size_t)q * B.ngp + i] = f[q];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tp[d][(size_t)q * B.ngp + i] = (q == d + 1) ? cf : 0.0;
+    }
+    const double es = block_sum_256(eacc, red);
+    const double ns = block_sum_256(nacc, red);
+    if (threadIdx.x == 0) {
+        R.epart[B.batch] = es;
+        R.npart[B.batch] = ns;
+    }
+}
+
 // ------------------------------------------------------ potential (SYR2K) --
 // Lower-triangle tile (I >= J) of V^j = Z Phi^T + Phi Z^T, 64 x 64, over all
 // points of the batch, added into V[f(row)][f(col)] (f ascending, so the
@@ -1848,6 +1976,75 @@ int run_integrate_uks(xc_context* c, int functional, const double* dPa, const do
     XC_TRY(launch_finish(nullptr, c->stream, dVb, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN));
     return launch_finish(nullptr, c->stream, dVa, c->nbf, (const double*)c->epart.p,
+                         (const double*)c->npart.p, c->n_batches, dEN);
+}
+
+// Meta-GGA wave (FP64). wb: the batches; wm: three copies of them (d = x,
+// y, z), each with gradient slab d in place of Phi and partial set d in
+// place of the density partials, n_all batches apart. Collocation and the
+// gradient slabs; the density contraction with Phi (rho, grad rho) and with
+// each gradient slab (tau); the functional; then Z and the potential
+// contraction with Phi, and Z_d = c d phi/dd with the potential contraction
+// against gradient slab d, for d = x, y, z (the Z slab is reused).
+static int launch_wave_meta(hipStream_t s, const WaveBatch* wb, const WaveBatch* wm,
+                            long long n_all, const int* gpre, const int* spre, int count,
+                            int gemm_tiles, int syr_tiles, const ReqDev* reqs, char* scr,
+                            int2* tmap, bool sph) {
+    hipLaunchKernelGGL((k_colloc<double, false>), dim3(count), dim3(256), 0, s, wb, reqs, scr);
+    XC_HIP(hipGetLastError());
+    if (sph) hipLaunchKernelGGL(k_grad<true>, dim3(count), dim3(256), 0, s, wb, reqs, scr);
+    else hipLaunchKernelGGL(k_grad<false>, dim3(count), dim3(256), 0, s, wb, reqs, scr);
+    XC_HIP(hipGetLastError());
+    const WaveBatch* sets[4] = {wb, wm, wm + n_all, wm + 2 * n_all};
+    if (gemm_tiles > 0) {
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, gpre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+        for (const WaveBatch* w : sets) {
+            hipLaunchKernelGGL((k_gemm_rho<true, double>), dim3(gemm_tiles), dim3(256), 0, s, w,
+                               (const int2*)tmap, gemm_tiles, reqs, scr);
+            XC_HIP(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(k_func_meta, dim3(count), dim3(256), 0, s, wb, reqs, scr);
+    XC_HIP(hipGetLastError());
+    if (syr_tiles > 0) {
+        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, spre, count,
+                           tmap);
+        XC_HIP(hipGetLastError());
+    }
+    for (const WaveBatch* w : sets) {
+        if (sph) hipLaunchKernelGGL((k_z<double, true>), dim3(count), dim3(256), 0, s, w, reqs, scr);
+        else hipLaunchKernelGGL((k_z<double, false>), dim3(count), dim3(256), 0, s, w, reqs, scr);
+        XC_HIP(hipGetLastError());
+        if (syr_tiles > 0) {
+            hipLaunchKernelGGL((k_syr2k<double, double>), dim3(syr_tiles), dim3(256), 0, s, w,
+                               (const int2*)tmap, syr_tiles, reqs, (const char*)scr);
+            XC_HIP(hipGetLastError());
+        }
+    }
+    return XC_OK;
+}
+
+int run_integrate_meta(xc_context* c, const double* dP, double* dV, double* dEN) {
+    const long long nn = (long long)c->nbf * c->nbf;
+    XC_TRY(launch_fill(c->stream, dV, nn, 0.0));
+    XC_TRY(dev_reserve(c->d_req, sizeof(ReqDev)));
+    XC_TRY(launch_put_req(c->stream, (ReqDev*)c->d_req.p, make_req(c, dP, dV)));
+    c->phi_cached_kind = 0;
+    const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
+    const WaveBatch* wm = (const WaveBatch*)c->d_wb_meta.p;
+    const long long n_all = (long long)c->h_wb.size();
+    const int* gpre = (const int*)c->d_gemm_pre.p;
+    const int* spre = (const int*)c->d_syr_pre.p;
+    for (const Wave& w : c->waves) {
+        if (w.count == 0) continue;
+        XC_TRY(launch_wave_meta(c->stream, wb + w.wb_off, wm + w.wb_off, n_all, gpre + w.pre_off,
+                                spre + w.pre_off, w.count, w.gemm_tiles, w.syr_tiles,
+                                (const ReqDev*)c->d_req.p, (char*)c->scratch.p,
+                                (int2*)c->d_tmap.p, c->any_pure));
+    }
+    return launch_finish(nullptr, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);
 }
 

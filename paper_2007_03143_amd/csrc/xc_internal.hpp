@@ -115,6 +115,25 @@ inline size_t batch_spin_bytes(const WaveBatch& w) {
     return 8 * (size_t)w.nmt * 4 * w.ngp;
 }
 
+// Extra wave-scratch bytes of one batch for meta-GGA integrations, after
+// its Phi, Z and partials: the three gradient slabs d phi/dx, /dy, /dz, then
+// three sets of partials for the kinetic energy density (set d from the
+// contraction of P with the d-th gradient slab).
+inline size_t batch_meta_bytes(const WaveBatch& w) {
+    return 8 * 3 * ((size_t)w.nbp * w.ngp + (size_t)w.nmt * 4 * w.ngp);
+}
+// Offsets (doubles, in the wave scratch) of gradient slab d and of partial
+// set d of a batch in a meta-GGA plan.
+__host__ __device__ inline long long meta_base_off(const WaveBatch& w) {
+    return w.part_off + (long long)w.nmt * 4 * w.ngp;
+}
+__host__ __device__ inline long long meta_grad_off(const WaveBatch& w, int d) {
+    return meta_base_off(w) + (long long)d * w.nbp * w.ngp;
+}
+__host__ __device__ inline long long meta_part_off(const WaveBatch& w, int d) {
+    return meta_base_off(w) + 3LL * w.nbp * w.ngp + (long long)d * w.nmt * 4 * w.ngp;
+}
+
 // Offset (doubles, from the batch's Phi slab) of its per-point digit scales.
 __host__ __device__ inline long long scale_row_off(const WaveBatch& w) {
     return (long long)w.nbp * w.ngp;
@@ -234,6 +253,10 @@ struct xc_context {
     bool spin_plan = false;      // batches carry a second (beta) set of partials
     std::vector<xc::WaveBatch> h_wb_beta;
     xc::DevBuf d_wb_beta;        // the batches with the beta partials and request 1
+    bool meta_plan = false;      // batches carry gradient slabs and kinetic-energy partials
+    std::vector<xc::WaveBatch> h_wb_meta;
+    xc::DevBuf d_wb_meta;        // three copies of the batches (d = x, y, z): Phi slab ->
+                                 // gradient slab d, partials -> partial set d
     xc::DevBuf epart, npart;
     xc::DevBuf d_req;            // one ReqDev for the context's own integrations
     xc::DevBuf pdig, pscale;     // digits and row scales of P (split-BF16 mode)
@@ -308,6 +331,8 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
                 char* scratch, int* d_tmap, bool colloc, bool sph);
 // Spin-unrestricted integration (FP64) of a context planned with
+// meta_plan: meta-GGA (TPSS), FP64, P in, V and (E_xc, N_e) out.
+int run_integrate_meta(xc_context* c, const double* dP, double* dV, double* dEN);
 // spin_plan: P^a, P^b in, V^a, V^b and (E_xc, N_e) out.
 int run_integrate_uks(xc_context* c, int functional, const double* dPa, const double* dPb,
                       double* dVa, double* dVb, double* dEN);

@@ -123,17 +123,19 @@ class XcEngine:
 
 
 def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None, exclude=(),
-          cache_phi=True):
+          cache_phi=True, log_every=1):
     """Run the request stream; returns a summary dict. keep_v(i) -> bool selects
     requests whose V matrices are copied back (for accuracy checks); requests
     whose index is in `exclude` are served like the others but left out of
-    the throughput and latency figures."""
+    the throughput and latency figures. log(msg), if given, hears of every
+    log_every-th finished request."""
     import torch
     eng = XcEngine(hbm_budget, wave_bytes, cache_phi=cache_phi)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
     nxt = 0
     inflight = {}      # ticket -> (request index, submit time, P, V, EN)
     n_done_int = 0
+    n_done_req = 0
     points_done = 0
     t0 = time.perf_counter()
 
@@ -185,9 +187,10 @@ def serve(requests, hbm_budget=0, wave_bytes=0, keep_v=None, log=None, exclude=(
                     eng.release(r.req_id)
                     if isinstance(r.densities, DeviceDensities):
                         r.densities.release()
-                    if log:
-                        log(f"request {i} {r.name} done: {len(r.results)} iterations, "
-                            f"t = {r.t_done:.3f} s")
+                    n_done_req += 1
+                    if log and n_done_req % log_every == 0:
+                        log(f"request {i} {r.name} done ({n_done_req} of {len(requests)}): "
+                            f"{len(r.results)} iterations, t = {r.t_done:.3f} s")
         wall = time.perf_counter() - t0
         st = eng.stats()
     finally:

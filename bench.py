@@ -151,9 +151,10 @@ def roofline(st, timing, steps, w, functional):
             "launches_per_step": launches}, phase_ms
 
 
-def fp64_section(w, functional, steps, warmup, wave_gb, batch_merge, singles):
+def fp64_section(w, functional, steps, warmup, wave_gb, batch_merge, singles, warm_steps=None):
     """Cold steps (grid build + integration) timed as the contract asks, then
-    warm integrations (grid reused); returns (ctx, P, result dict)."""
+    warm integrations (grid reused; warm_steps of them back to back, default
+    steps); returns (ctx, P, result dict)."""
     import torch
     from paper_2007_03143_amd import XcContext
     from workloads import grid_spec_dict
@@ -185,12 +186,13 @@ def fp64_section(w, functional, steps, warmup, wave_gb, batch_merge, singles):
     ms_step = (t1 - t0) * 1e3 / steps
     n_nom = w.n_points_nominal
 
+    n_warm = steps if warm_steps is None else max(1, min(steps, warm_steps))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    for i in range(steps):
+    for i in range(n_warm):
         ctx.integrate(P, functional)
     torch.cuda.synchronize()
-    ms_warm = (time.perf_counter() - t2) * 1e3 / steps
+    ms_warm = (time.perf_counter() - t2) * 1e3 / n_warm
     EN = ctx.EN.cpu().numpy().copy()
     V = ctx.V.cpu().numpy()
     log(f"  warm {ms_warm:.1f} ms/step; E_xc {EN[0]!r} N_e {EN[1]!r}")
@@ -201,7 +203,7 @@ def fp64_section(w, functional, steps, warmup, wave_gb, batch_merge, singles):
         torch.cuda.synchronize()
         per.append((time.perf_counter() - ta) * 1e3)
     warm = {"value": n_nom / (ms_warm * 1e-3), "ms_per_step": ms_warm,
-            "step": "integration with the grid reused",
+            "step": "integration with the grid reused", "back_to_back": n_warm,
             "median_ms_single": float(np.median(per)) if per else None,
             "single_runs": len(per)}
     if st["n_waves"] == 1:
@@ -209,10 +211,10 @@ def fp64_section(w, functional, steps, warmup, wave_gb, batch_merge, singles):
         ctx.integrate(P, functional)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        for i in range(steps):
+        for i in range(n_warm):
             ctx.integrate(P, functional)
         torch.cuda.synchronize()
-        ms_cache = (time.perf_counter() - t2) * 1e3 / steps
+        ms_cache = (time.perf_counter() - t2) * 1e3 / n_warm
         ENc = ctx.EN.cpu().numpy()
         ctx.set_phi_cache(False)
         warm["phi_cache"] = {"value": n_nom / (ms_cache * 1e-3), "ms_per_step": ms_cache,
@@ -527,8 +529,10 @@ def main():
 
     with Section(f"headline {args.workload} fp64"):
         w, functional = make_workload(args.workload)
+        # warm timing: 5 integrations back to back and 5 one by one (each
+        # about 3 s on the chain), enough for a stable mean
         ctx, P, head, ref = fp64_section(w, functional, args.steps, args.warmup, args.wave_gb,
-                                         args.batch_merge, singles=5)
+                                         args.batch_merge, singles=5, warm_steps=5)
         ctx.close()
         del P
         torch.cuda.empty_cache()

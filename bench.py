@@ -409,6 +409,14 @@ def serving_run(n_req, s_pool_result, seed=5, load=0.7, n_sat=100, check_frac=0.
                    log_every=25)
     saturation = closed["points_per_s"]
     log(f"  closed-loop on {n_sat} requests: {saturation / 1e6:.1f} Mpts/s")
+    # the same closed loop without the per-request Phi store (every SCF
+    # iteration recomputes Phi)
+    closed_nc = serve([make(i, 0.0) for i in range(n_sat)], wave_bytes=2 << 30, log=log,
+                      log_every=50, cache_phi=False)
+    log(f"  closed-loop without the Phi store: {closed_nc['points_per_s'] / 1e6:.1f} Mpts/s")
+    cache_cmp = {k: {"points_per_s": r["points_per_s"], "latency_p50_ms": r["latency_p50_ms"],
+                     "latency_p99_ms": r["latency_p99_ms"]}
+                 for k, r in (("phi_store_on", closed), ("phi_store_off", closed_nc))}
     lam = load * saturation / mean_pts
     rng = np.random.default_rng([seed, 99])
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
@@ -462,6 +470,7 @@ def serving_run(n_req, s_pool_result, seed=5, load=0.7, n_sat=100, check_frac=0.
     summary.update({"requests": n_req, "load": load, "arrival_rate_per_s": lam,
                     "saturation_points_per_s": saturation,
                     "saturation_measured_on": f"first {n_sat} requests, closed loop",
+                    "closed_loop_phi_store": cache_cmp,
                     "mean_points_per_request": mean_pts, "oracle_checks": checks,
                     "oracle_checks_worst_abs": worst,
                     "twin_requests_excluded_from_latency": len(twins),

@@ -526,3 +526,20 @@ def test_chain600_full_grid_atoms_match_golden():
         assert abs(E - g["E_xc"]) <= TOL_E and abs(N - g["N_e"]) <= TOL_E
         assert dv <= TOL_V and drs <= TOL_V
         assert np.array_equal(V, V.T)
+
+
+@pytest.mark.parametrize("prec", ["bf16", pytest.param("fp32", marks=pytest.mark.xfail(
+    strict=True, reason="FP32 collocation and contractions: the rounding errors of P and "
+                        "Phi are coherent over a radial shell's equal s-function values, "
+                        "-8.4e-6 Eh on this cluster (1.1e-7 on one water)"))])
+def test_mixed_whole_cluster_within_1e6_of_fp64(prec):
+    """The mixed-precision bound on the whole 64-water cluster (192 atoms,
+    100 x 590), against the FP64 path: split BF16 meets |dE_xc| <= 1e-6 Eh;
+    all-FP32 does not (expected failure, kept to record it)."""
+    from gpu_util import gpu_integrate_prec
+    w = cfg_water_cluster()
+    E, N, V, st = gpu_integrate(w, "pbe")
+    Em, Nm, Vm, _ = gpu_integrate_prec(w, "pbe", prec)
+    say(f"case water64 whole cluster {prec}: dE {Em - E:.3e} dN {Nm - N:.3e} "
+        f"max dV {np.abs(Vm - V).max():.3e}")
+    assert abs(Em - E) <= 1e-6 and abs(Nm - N) <= 1e-6

@@ -19,6 +19,21 @@ def random_density(S, n_occ, seed=0):
     return np.ascontiguousarray(0.5 * (P + P.T))
 
 
+def open_shell_densities(S, n_alpha, n_beta, seed=0):
+    """P^a = C C^T over n_alpha S-orthonormalised random orbitals and P^b over
+    their first n_beta (n_beta <= n_alpha): both positive semidefinite,
+    tr(P^a S) = n_alpha, tr(P^b S) = n_beta."""
+    rng = np.random.default_rng([seed, 4])
+    nb = S.shape[0]
+    C = rng.normal(size=(nb, n_alpha))
+    M = C.T @ S @ C
+    ev, U = np.linalg.eigh(M)
+    C = C @ (U / np.sqrt(ev)) @ U.T
+    Pa = C @ C.T
+    Pb = C[:, :n_beta] @ C[:, :n_beta].T
+    return (np.ascontiguousarray(0.5 * (Pa + Pa.T)), np.ascontiguousarray(0.5 * (Pb + Pb.T)))
+
+
 def perturbed_density(P0, norm, seed):
     rng = np.random.default_rng([seed, 2])
     d = rng.normal(size=P0.shape)

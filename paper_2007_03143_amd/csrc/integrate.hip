@@ -279,40 +279,23 @@ __device__ inline void z_shell(double dx, double dy, double dz, double rad, doub
     }
 }
 
-// phi of the (L+1)(L+2)/2 components of one shell at one point, written
-// down the rows starting at out; returns the largest magnitude (FP64).
-template <int L, typename T>
-__device__ inline double phi_shell(double dx, double dy, double dz, double rad, T* out,
-                                   int ngp) {
-    double xp[L + 1], yp[L + 1], zp[L + 1];
-    xp[0] = yp[0] = zp[0] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= L; ++k) {
-        xp[k] = xp[k - 1] * dx;
-        yp[k] = yp[k - 1] * dy;
-        zp[k] = zp[k - 1] * dz;
-    }
-    double mx = 0.0;
-    int c = 0;
-#pragma unroll
-    for (int l = L; l >= 0; --l) {
-#pragma unroll
-        for (int m = L - l; m >= 0; --m) {
-            const double v = xp[l] * yp[m] * zp[L - l - m] * rad;
-            mx = fmax(mx, fabs(v));
-            out[(size_t)c * ngp] = T(v);
-            ++c;
-        }
-    }
-    return mx;
-}
-
-// phi of the 2L+1 spherical functions of a shell (L = 2, 3) at one point:
-// the Cartesian components are formed in registers and combined; returns
-// the largest magnitude written.
-template <int L, typename T>
-__device__ inline double phi_shell_sph(double dx, double dy, double dz, double rad, T* out,
-                                       int ngp) {
+// One workgroup per batch; wave w evaluates shells w, w+4, ... of the
+// batch's screened list, one lane per point, so a wave never diverges on
+// the contraction length. Points of the batch are staged in LDS. Values are
+// formed in FP64 in every mode and rounded once on store. SCALE (split-BF16
+// mode): a first pass over the shells keeps only the largest magnitude
+// max_mu |phi_mu(r_i)| of every point as a running maximum in LDS (the bit
+// patterns of non-negative doubles order like unsigned integers); the digit
+// scale of a point is the least power of two not below it (1 where all are
+// zero) and goes to the batch's scale row; a second pass forms the values
+// again, bit for bit the same, and cuts each into its four digits
+// (digits_packed) straight into the Phi slab.
+// phi of one shell at one point in one of three modes: MODE 0 stores the
+// values (type T), MODE 1 only returns their largest magnitude, MODE 2
+// stores the digits of value * inv (T = unsigned long long).
+template <int L, int MODE, typename T>
+__device__ inline double phi_shell_mode(const ShellDev& sh, double dx, double dy, double dz,
+                                        double rad, T* out, int ngp, double inv) {
     constexpr int NC = (L + 1) * (L + 2) / 2;
     double xp[L + 1], yp[L + 1], zp[L + 1];
     xp[0] = yp[0] = zp[0] = 1.0;
@@ -322,37 +305,73 @@ __device__ inline double phi_shell_sph(double dx, double dy, double dz, double r
         yp[k] = yp[k - 1] * dy;
         zp[k] = zp[k - 1] * dz;
     }
-    double v[NC];
-    int c = 0;
-#pragma unroll
-    for (int l = L; l >= 0; --l)
-#pragma unroll
-        for (int m = L - l; m >= 0; --m) v[c++] = xp[l] * yp[m] * zp[L - l - m];
     double mx = 0.0;
+    auto put = [&](int r, double v) {
+        mx = fmax(mx, fabs(v));
+        if constexpr (MODE == 0) out[(size_t)r * ngp] = T(v);
+        if constexpr (MODE == 2) out[(size_t)r * ngp] = digits_packed(v * inv);
+    };
+    if (L >= 2 && sh.pure) {
+        double v[NC];
+        int c = 0;
 #pragma unroll
-    for (int m = 0; m < 2 * L + 1; ++m) {
-        double a = 0.0;
+        for (int l = L; l >= 0; --l)
 #pragma unroll
-        for (int k = 0; k < NC; ++k)
-            if (sph<L>(m, k) != 0.0) a = fma(sph<L>(m, k), v[k], a);
-        a *= rad;
-        mx = fmax(mx, fabs(a));
-        out[(size_t)m * ngp] = T(a);
+            for (int m = L - l; m >= 0; --m) v[c++] = xp[l] * yp[m] * zp[L - l - m];
+#pragma unroll
+        for (int m = 0; m < 2 * L + 1; ++m) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                if (sph<L>(m, k) != 0.0) a = fma(sph<L>(m, k), v[k], a);
+            put(m, a * rad);
+        }
+    } else {
+        int c = 0;
+#pragma unroll
+        for (int l = L; l >= 0; --l)
+#pragma unroll
+            for (int m = L - l; m >= 0; --m) {
+                put(c, xp[l] * yp[m] * zp[L - l - m] * rad);
+                ++c;
+            }
     }
     return mx;
 }
 
-// One workgroup per batch; wave w evaluates shells w, w+4, ... of the
-// batch's screened list, one lane per point, so a wave never diverges on
-// the contraction length. Points of the batch are staged in LDS. Values are
-// formed in FP64 in every mode and rounded once on store. SCALE (split-BF16
-// mode): the FP64 values go to the Z slab (free until the Z kernel) while
-// the digit scale of every point, the least power of two not below
-// max_mu |phi_mu(r_i)| over the batch's functions (1 where all are zero), is
-// kept as a running maximum in LDS (the bit patterns of non-negative doubles
-// order like unsigned integers); after a barrier the scales go to the
-// batch's scale row and every value is cut into its four digits
-// (digits_packed), which fill the Phi slab.
+// One collocation pass over the batch's shells (wave-strided) and points
+// (lane-strided) in the given mode; MODE 1 folds each point's largest
+// magnitude into smax, MODE 2 reads each point's inverse scale from it.
+template <int MODE, typename T>
+__device__ inline void colloc_pass(const WaveBatch& B, const ReqG& R, const double* sx,
+                                   const double* sy, const double* sz,
+                                   unsigned long long* smax, T* Phi) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    for (int sl = wave; sl < B.nshell; sl += 4) {
+        const int s = R.shell_list[B.shell_off + sl];
+        const int loff = R.shell_loff[B.shell_off + sl];
+        const ShellDev sh = load_shell(R.shells + s);
+        for (int i = lane; i < B.ngp; i += 64) {
+            double dx, dy, dz, rad, drad;
+            const double r2 = dist2_nc(sx[i], sy[i], sz[i], sh, dx, dy, dz);
+            if (i < B.ng) shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
+            else rad = drad = 0.0;
+            T* out = Phi + (size_t)loff * B.ngp + i;
+            const double inv = MODE == 2 ? __longlong_as_double((long long)smax[i]) : 0.0;
+            double mx;
+            switch (sh.L) {
+                case 0: mx = phi_shell_mode<0, MODE, T>(sh, dx, dy, dz, rad, out, B.ngp, inv); break;
+                case 1: mx = phi_shell_mode<1, MODE, T>(sh, dx, dy, dz, rad, out, B.ngp, inv); break;
+                case 2: mx = phi_shell_mode<2, MODE, T>(sh, dx, dy, dz, rad, out, B.ngp, inv); break;
+                default: mx = phi_shell_mode<3, MODE, T>(sh, dx, dy, dz, rad, out, B.ngp, inv); break;
+            }
+            if (MODE == 1 && mx > 0.0)
+                atomicMax(&smax[i], (unsigned long long)__double_as_longlong(mx));
+        }
+    }
+}
+
 template <typename T, bool SCALE>
 __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb,
                                                 const ReqDev* __restrict__ reqs,
@@ -372,39 +391,12 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
     }
     __syncthreads();
     char* phi = phi_slab(B, R, scratch);
-    T* Phi = SCALE ? (T*)(scratch + 8 * B.z_off) : (T*)phi;
-    // zero the padding rows n_b .. n_bp - 1
+    // zero the padding rows n_b .. n_bp - 1 (a zero value has zero digits)
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
-    for (long long k = threadIdx.x; k < npad; k += blockDim.x) Phi[(size_t)B.nb * B.ngp + k] = T(0);
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    for (int sl = wave; sl < B.nshell; sl += 4) {
-        const int s = R.shell_list[B.shell_off + sl];
-        const int loff = R.shell_loff[B.shell_off + sl];
-        const ShellDev sh = load_shell(R.shells + s);
-        for (int i = lane; i < B.ngp; i += 64) {
-            double dx, dy, dz, rad, drad;
-            const double r2 = dist2_nc(sx[i], sy[i], sz[i], sh, dx, dy, dz);
-            if (i < B.ng) shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
-            else rad = drad = 0.0;
-            T* out = Phi + (size_t)loff * B.ngp + i;
-            double mx;
-            if (sh.pure) {
-                if (sh.L == 2) mx = phi_shell_sph<2, T>(dx, dy, dz, rad, out, B.ngp);
-                else mx = phi_shell_sph<3, T>(dx, dy, dz, rad, out, B.ngp);
-            } else {
-                switch (sh.L) {
-                    case 0: mx = phi_shell<0, T>(dx, dy, dz, rad, out, B.ngp); break;
-                    case 1: mx = phi_shell<1, T>(dx, dy, dz, rad, out, B.ngp); break;
-                    case 2: mx = phi_shell<2, T>(dx, dy, dz, rad, out, B.ngp); break;
-                    default: mx = phi_shell<3, T>(dx, dy, dz, rad, out, B.ngp); break;
-                }
-            }
-            if (SCALE && mx > 0.0)
-                atomicMax(&smax[i], (unsigned long long)__double_as_longlong(mx));
-        }
-    }
     if constexpr (SCALE) {
+        unsigned long long* dig = (unsigned long long*)phi;
+        for (long long k = threadIdx.x; k < npad; k += blockDim.x) dig[(size_t)B.nb * B.ngp + k] = 0ull;
+        colloc_pass<1, unsigned long long>(B, R, sx, sy, sz, smax, dig);
         __syncthreads();
         double* sc = (double*)phi + scale_row_off(B);
         for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
@@ -413,16 +405,15 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
             (void)frexp(m, &e);  // m = f 2^e with f in [0.5, 1), so m <= 2^e
             e = max(e, -1000);   // 1 / scale stays finite
             sc[i] = m > 0.0 ? ldexp(1.0, e) : 1.0;
-            sx[i] = m > 0.0 ? ldexp(1.0, -e) : 1.0;   // the exact inverse, for the cut
+            // the exact inverse, for the cut (kept in smax from here on)
+            smax[i] = (unsigned long long)__double_as_longlong(m > 0.0 ? ldexp(1.0, -e) : 1.0);
         }
         __syncthreads();
-        const double* val = (const double*)Phi;
-        unsigned long long* dig = (unsigned long long*)phi;
-        for (int r = 0; r < B.nbp; ++r)
-            for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
-                const size_t k = (size_t)r * B.ngp + i;
-                dig[k] = digits_packed(val[k] * sx[i]);
-            }
+        colloc_pass<2, unsigned long long>(B, R, sx, sy, sz, smax, dig);
+    } else {
+        T* Phi = (T*)phi;
+        for (long long k = threadIdx.x; k < npad; k += blockDim.x) Phi[(size_t)B.nb * B.ngp + k] = T(0);
+        colloc_pass<0, T>(B, R, sx, sy, sz, smax, Phi);
     }
 }
 

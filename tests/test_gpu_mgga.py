@@ -112,3 +112,40 @@ def test_unsupported_combinations_rejected():
             ctx.integrate_uks(P / 2, P / 2, "tpss")
     finally:
         ctx.close()
+
+
+def test_cluster_atoms_match_golden():
+    """TPSS on the 64-water cluster (192 atoms, 1600 functions, 100 x 590),
+    one parent atom at a time (an O and an H), against stored oracle values
+    (tests/golden/cluster64_ext_atoms.json, written by
+    make_cluster64_ext_golden.py from the oracle alone): E_xc, N_e, V on a
+    seeded sample of entries and every row sum, to 1e-10."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "cluster64_ext_atoms.json")))
+    w = cfg_water_cluster()
+    assert (w.n_rad, w.n_ang, w.nbf) == (gold["n_rad"], gold["n_ang"], gold["nbf"])
+    for g in gold["atoms"]:
+        mask = np.zeros(w.natoms, np.uint8)
+        mask[g["atom"]] = 1
+        say(f"case tpss cluster64 atom {g['atom']} (Z {g['Z']})")
+        E, N, V, st = gpu_integrate(w, "tpss", atom_mask=mask)
+        t = g["tpss"]
+        r, c = np.array(g["sample_rows"]), np.array(g["sample_cols"])
+        dv = np.abs(V[r, c] - np.array(t["V"]["sample_values"])).max()
+        drs = np.abs(V.sum(axis=1) - np.array(t["V"]["row_sums"])).max()
+        say(f"  dE {E - t['E_xc']:.3e} dN {N - t['N_e']:.3e} sampled max dV {dv:.3e} "
+            f"max d(row sum) {drs:.3e} max n_b {st['max_nb']}")
+        assert abs(E - t["E_xc"]) <= TOL and abs(N - t["N_e"]) <= TOL
+        assert dv <= TOL and drs <= TOL
+        assert np.array_equal(V, V.T)
+
+
+@pytest.mark.parametrize("functional", ["tpss"])
+def test_becke_partition_parity(functional):
+    """TPSS with Becke's size-adjusted partition (water, 40 x 110)."""
+    w = cfg_water(n_rad=40, n_ang=110)
+    say("case tpss water becke")
+    g = gpu_integrate(w, "tpss", partition="becke", becke_radius=w.becke_radius)
+    _compare("tpss becke", g, _oracle(w, partition="becke", becke_radius=w.becke_radius))

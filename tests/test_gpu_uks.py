@@ -130,3 +130,56 @@ def test_mixed_precision_rejected():
             ctx.integrate_uks(P, P, "pbe", precision="fp32")
     finally:
         ctx.close()
+
+
+def _golden_ext():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "cluster64_ext_atoms.json")))
+
+
+def _check_v(tag, V, rec, r, c):
+    dv = np.abs(V[r, c] - np.array(rec["sample_values"])).max()
+    drs = np.abs(V.sum(axis=1) - np.array(rec["row_sums"])).max()
+    say(f"  {tag}: sampled max dV {dv:.3e} ({len(r)} entries), max d(row sum) {drs:.3e}")
+    assert dv <= TOL and drs <= TOL
+    assert np.array_equal(V, V.T)
+
+
+def test_cluster_atoms_match_golden():
+    """The 64-water cluster (192 atoms, 1600 functions, 100 x 590) with an
+    open-shell density pair (P^a over 256 orbitals, P^b over the first 250),
+    one parent atom at a time (an O and an H), against stored oracle values
+    (tests/golden/cluster64_ext_atoms.json, written by
+    make_cluster64_ext_golden.py from the oracle alone): E_xc, N_e, V^a and
+    V^b on a seeded sample of entries and every row sum, to 1e-10."""
+    from workloads.density import open_shell_densities
+    gold = _golden_ext()
+    w = cfg_water_cluster()
+    assert (w.n_rad, w.n_ang, w.nbf) == (gold["n_rad"], gold["n_ang"], gold["nbf"])
+    o = gold["open_shell"]
+    Pa, Pb = open_shell_densities(w.S, o["n_alpha"], o["n_beta"], seed=o["seed"])
+    for g in gold["atoms"]:
+        mask = np.zeros(w.natoms, np.uint8)
+        mask[g["atom"]] = 1
+        say(f"case uks cluster64 atom {g['atom']} (Z {g['Z']})")
+        E, N, Va, Vb, st = _gpu_uks(w, Pa, Pb, "pbe", atom_mask=mask)
+        u = g["uks_pbe"]
+        say(f"  dE {E - u['E_xc']:.3e} dN {N - u['N_e']:.3e} max n_b {st['max_nb']}")
+        assert abs(E - u["E_xc"]) <= TOL and abs(N - u["N_e"]) <= TOL
+        r, c = np.array(g["sample_rows"]), np.array(g["sample_cols"])
+        _check_v("Va", Va, u["Va"], r, c)
+        _check_v("Vb", Vb, u["Vb"], r, c)
+
+
+def test_becke_partition_parity():
+    """Open-shell water, PBE, Becke's size-adjusted partition (40 x 110)."""
+    w = cfg_water(n_rad=40, n_ang=110)
+    Pa, Pb = _open_shell(w)
+    say("case uks water becke")
+    g = _gpu_uks(w, Pa, Pb, "pbe", partition="becke", becke_radius=w.becke_radius)
+    o = integrate_uks(w.coords, w.mk_alpha, w.basis, Pa, Pb, "pbe", w.n_rad, w.ang,
+                      ssf_a=w.ssf_a, screen_eta=w.screen_eta, rho_thresh=w.rho_thresh,
+                      partition="becke", becke_radius=w.becke_radius)
+    _compare("pbe becke", g, o)

@@ -288,6 +288,89 @@ def mixed_section(ctx, P, w, functional, precs, ref, steps):
     return out
 
 
+def extensions_section(ctx, P, w, ms_pbe, st, steps=3):
+    """The scope's extensions on the 64-water cluster, FP64, warm (grid
+    reused): spin-unrestricted PBE (an open-shell pair of densities) and
+    TPSS on the same context; then Becke's partition on the SFG grid
+    (175 x 974, cold: grid build + integration) and spherical d/f shells on
+    their own contexts. Their parity with the oracle is in the GPU tests;
+    here: time, points/s and the contractions' useful FP64 rate (the
+    restricted contraction flops times the number of contraction passes)."""
+    import torch
+    from paper_2007_03143_amd import XcContext
+    from workloads import cfg_water_cluster, grid_spec_dict
+    from workloads.density import open_shell_densities
+    out = {}
+    n_nom = w.n_points_nominal
+    fl1 = 2.0 * st["sum_nb2_ng"] + 2.0 * (st["sum_nb2_ng"] + st["sum_nb_ng"])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    Pa, Pb = open_shell_densities(w.S, 4 * w.natoms // 3, 4 * w.natoms // 3 - 6, seed=2)
+    Pa_d, Pb_d = torch.from_numpy(Pa).cuda(), torch.from_numpy(Pb).cuda()
+    ms = timed(lambda: ctx.integrate_uks(Pa_d, Pb_d, "pbe"))
+    out["uks_pbe"] = {"ms": ms, "points_per_s": n_nom / (ms * 1e-3),
+                      "vs_restricted_pbe": ms / ms_pbe,
+                      "contraction_tflops_if_all_time": 2 * fl1 / (ms * 1e-3) / 1e12,
+                      "E_xc": float(ctx.EN[0])}
+    log(f"  uks pbe: {ms:.1f} ms ({ms / ms_pbe:.2f}x restricted)")
+    ms = timed(lambda: ctx.integrate(P, "tpss"))
+    out["tpss"] = {"ms": ms, "points_per_s": n_nom / (ms * 1e-3),
+                   "vs_restricted_pbe": ms / ms_pbe,
+                   "contraction_tflops_if_all_time": 4 * fl1 / (ms * 1e-3) / 1e12,
+                   "E_xc": float(ctx.EN[0])}
+    log(f"  tpss: {ms:.1f} ms ({ms / ms_pbe:.2f}x restricted pbe)")
+    del Pa_d, Pb_d
+
+    wb = cfg_water_cluster(n_rad=175, n_ang=974)
+    cb = XcContext(wb.coords, wb.mk_alpha, wb.basis,
+                   grid_spec_dict(wb, partition="becke", becke_radius=wb.becke_radius))
+    try:
+        Pd = torch.from_numpy(wb.P).cuda()
+        def cold():
+            cb.build_grid()
+            cb.integrate(Pd, "pbe")
+        ms = timed(cold)
+        cb.set_timing(True)
+        cold()
+        torch.cuda.synchronize()
+        tm = cb.timing()
+        cb.set_timing(False)
+        sb = cb.stats()
+        out["becke_sfg_175x974"] = {
+            "ms_cold": ms, "points_per_s": wb.n_points_nominal / (ms * 1e-3),
+            "n_points_nominal": wb.n_points_nominal, "n_waves": sb["n_waves"],
+            "weights_ms": tm["weights"]["ms"], "E_xc": float(cb.EN[0])}
+        log(f"  becke sfg: {ms:.1f} ms cold, weights {tm['weights']['ms']:.1f} ms")
+    finally:
+        cb.close()
+        torch.cuda.empty_cache()
+
+    ws = cfg_water_cluster(polarisation=True, pure=True)
+    cs = XcContext(ws.coords, ws.mk_alpha, ws.basis, grid_spec_dict(ws))
+    try:
+        Pd = torch.from_numpy(ws.P).cuda()
+        cs.build_grid()
+        ms = timed(lambda: cs.integrate(Pd, "pbe"))
+        ss = cs.stats()
+        fls = 2.0 * ss["sum_nb2_ng"] + 2.0 * (ss["sum_nb2_ng"] + ss["sum_nb_ng"])
+        out["spherical_fd"] = {"ms": ms, "nbf": ws.nbf, "points_per_s": ws.n_points_nominal / (ms * 1e-3),
+                               "contraction_tflops_if_all_time": fls / (ms * 1e-3) / 1e12,
+                               "E_xc": float(cs.EN[0])}
+        log(f"  spherical d/f shells ({ws.nbf} functions): {ms:.1f} ms")
+    finally:
+        cs.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def oracle_atom_check(w, functional, atom, precs):
     """Errors against the FP64 oracle on one parent atom's grid (the
     partition over all atoms), for FP64 and every mixed mode."""
@@ -503,6 +586,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 3 times (a plain "
                          "copy kernel of known size for scaling HBM byte counters)")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the spin-unrestricted, TPSS, Becke/SFG and spherical timings")
     ap.add_argument("--only-fp64", action="store_true",
                     help="only the headline FP64 section (for profiling runs)")
     args = ap.parse_args()
@@ -562,6 +647,8 @@ def main():
                                                0.0, args.batch_merge, singles=10)
             precs = [p for p in args.mixed.split(",") if p]
             sec["mixed"] = mixed_section(ctx2, P2, w2, f2, precs, ref2, args.mixed_steps)
+            if not args.no_extensions:
+                sec["extensions"] = extensions_section(ctx2, P2, w2, ref2[2], ctx2.stats())
             ctx2.close()
             del P2
             torch.cuda.empty_cache()

@@ -479,21 +479,28 @@ __global__ __launch_bounds__(256) void k_ssf_wave(long long n, int npa, const in
 }
 
 // ------------------------------------------ Becke partition, one wave a point --
-// Becke's cell function s(nu) = (1 - p(p(p(nu))))/2, p(x) = 3x/2 - x^3/2.
-__device__ inline double becke_s(double nu) {
-    double f = nu;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) f = f * (1.5 - 0.5 * f * f);
-    return 0.5 * (1.0 - f);
+// Becke's cell function is s(nu) = (1 - p(p(p(nu))))/2, p(x) = 3x/2 - x^3/2;
+// p is odd, so s(-nu) = 1 - s(nu) = (1 + p(p(p(nu))))/2.
+__device__ inline double wave_sum(double v) {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // Weights with Becke's partition (molecules up to kSsfWaveMaxAtoms atoms).
 // No factor is exactly 0 or 1 away from the nuclei, so every point needs
-// every atom's cell product: the wave takes the points of its lanes one at a
-// time, lane l holds atoms l, l + 64, ... (their distances to the point), and
-// each P_C = prod_{B != C} s(nu_CB), nu_CB = mu_CB + a_CB (1 - mu_CB^2), is
-// spread over the lanes and finished by a butterfly. Points of zero weight
-// are skipped.
+// every atom's cell product. The wave takes the points of its lanes PTS at
+// a time (4 up to 256 atoms, 2 up to 512, then 1: the registers they take); lane l holds atoms B = l, l + 64, ... with their distances to each
+// of those points and accumulates their own products P_B = prod_{C != B}
+// s(nu_BC) while the wave steps through C, using s(nu_BC) = s(-nu_CB) =
+// (1 + p(p(p(nu_CB))))/2 (mu and the size adjustment are antisymmetric), so
+// that every lane reads row C of the pair tables at its own column B
+// (consecutive across the lanes), once for the PTS points, and no
+// cross-lane product is needed; the wave sums the P_B of each point at the
+// end. d_C of a point is read from the lane that holds atom C. Points of
+// zero weight are skipped.
 template <int NPER>
 __global__ __launch_bounds__(256) void k_becke_wave(long long n, int npa, const int* gatoms,
                                                     const double4* atoms_g,
@@ -501,6 +508,7 @@ __global__ __launch_bounds__(256) void k_becke_wave(long long n, int npa, const 
                                                     int natoms, const double* X,
                                                     const double* Y, const double* Z,
                                                     double* W) {
+    constexpr int PTS = NPER <= 4 ? 4 : NPER <= 8 ? 2 : 1;
     extern __shared__ double4 sat[];
     for (int k = threadIdx.x; k < natoms; k += blockDim.x) sat[k] = atoms_g[k];
     __syncthreads();
@@ -521,35 +529,75 @@ __global__ __launch_bounds__(256) void k_becke_wave(long long n, int npa, const 
     }
     unsigned long long todo = __ballot(need);
     while (todo) {
-        const int l = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const double px = readlane_f64(x, l), py = readlane_f64(y, l), pz = readlane_f64(z, l);
-        const int pA = __builtin_amdgcn_readlane(A, l);
-        double d[NPER];
+        // up to PTS points of the wave's lanes (slots past the last repeat it)
+        int ln[PTS];
 #pragma unroll
-        for (int j = 0; j < NPER; ++j) {
-            const int B = lane + 64 * j;
-            d[j] = B < natoms ? sqrt(dist2_to(sat[B], px, py, pz)) : 0.0;
+        for (int p = 0; p < PTS; ++p) {
+            ln[p] = __ffsll((unsigned long long)todo) - 1;
+            if (todo & (todo - 1)) todo &= todo - 1;
+            else if (p + 1 < PTS) {
+#pragma unroll
+                for (int r = p + 1; r < PTS; ++r) ln[r] = ln[p];
+                todo = 0;
+                break;
+            } else {
+                todo = 0;
+            }
         }
-        double sum = 0.0, PA = 0.0;
+        double d[PTS][NPER], q[PTS][NPER];
+#pragma unroll
+        for (int p = 0; p < PTS; ++p) {
+            const double px = readlane_f64(x, ln[p]), py = readlane_f64(y, ln[p]),
+                         pz = readlane_f64(z, ln[p]);
+#pragma unroll
+            for (int j = 0; j < NPER; ++j) {
+                const int B = lane + 64 * j;
+                d[p][j] = B < natoms ? sqrt(dist2_to(sat[B], px, py, pz)) : 0.0;
+                q[p][j] = 1.0;
+            }
+        }
         for (int C = 0; C < natoms; ++C) {
-            const double dC = sqrt(dist2_to(sat[C], px, py, pz));
+            const int jc = C >> 6, lc = C & 63;
+            double dC[PTS];
+#pragma unroll
+            for (int p = 0; p < PTS; ++p) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < NPER; ++j)
+                    if (j == jc) v = d[p][j];
+                dC[p] = readlane_f64(v, lc);
+            }
             const double* ir = invR + (size_t)C * natoms;
             const double* ar = adj + (size_t)C * natoms;
-            double p = 1.0;
 #pragma unroll
             for (int j = 0; j < NPER; ++j) {
                 const int B = lane + 64 * j;
                 if (B < natoms && B != C) {
-                    const double mu = (dC - d[j]) * ir[B];
-                    p *= becke_s(mu + ar[B] * (1.0 - mu * mu));
+                    const double irb = ir[B], arb = ar[B];
+#pragma unroll
+                    for (int p = 0; p < PTS; ++p) {
+                        const double mu = (dC[p] - d[p][j]) * irb;
+                        double f = mu + arb * (1.0 - mu * mu);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) f = f * (1.5 - 0.5 * f * f);
+                        q[p][j] *= 0.5 * (1.0 + f);
+                    }
                 }
             }
-            const double PC = wave_product(p);
-            sum += PC;
-            if (C == pA) PA = PC;
         }
-        if (lane == l) W[i] = w * (PA / sum);
+#pragma unroll
+        for (int p = 0; p < PTS; ++p) {
+            const int pA = __builtin_amdgcn_readlane(A, ln[p]);
+            double qs = 0.0, qa = 0.0;
+#pragma unroll
+            for (int j = 0; j < NPER; ++j) {
+                if (lane + 64 * j < natoms) qs += q[p][j];
+                if (j == (pA >> 6)) qa = q[p][j];
+            }
+            const double sum = wave_sum(qs);
+            const double PA = readlane_f64(qa, pA & 63);
+            if (lane == ln[p]) W[i] = w * (PA / sum);
+        }
     }
 }
 

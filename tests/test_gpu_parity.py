@@ -461,6 +461,40 @@ def test_becke_weights_match_oracle():
         assert np.all(np.abs(full - wo) <= 1e-13 * wq)
 
 
+@pytest.mark.parametrize("n_waters", [40, 120, 300])
+def test_becke_weights_many_atoms(n_waters):
+    """Becke weights with the size adjustment for 120, 360 and 900 atoms (4,
+    2 and 1 points per wave pass, up to 16 atoms per lane); the grids of two
+    parent atoms (an O and an H) on a 4 x 6 grid, the partition over every
+    atom on both sides."""
+    from paper_2007_03143_amd import XcContext
+    from workloads.molecules import water_cluster
+    from workloads.angular import lebedev_table
+    from workloads.configs import MK_ALPHA, BECKE_RADIUS
+    mol = water_cluster(n_waters, box=25.0 * (n_waters / 64.0) ** (1.0 / 3.0), seed=13)
+    basis = make_basis(mol.Z)
+    mk = np.array([MK_ALPHA[int(z)] for z in mol.Z])
+    rad = np.array([BECKE_RADIUS[int(z)] for z in mol.Z])
+    ang = lebedev_table(6)
+    mask = np.zeros(mol.natoms, np.uint8)
+    mask[[0, 3 * (n_waters // 2) + 1]] = 1
+    say(f"case becke weights {mol.natoms} atoms")
+    grid = dict(n_rad=4, n_ang=6, ang=ang, ssf_a=0.64, screen_eta=1e-10, batch_max=512,
+                rho_thresh=1e-15, atom_mask=mask, partition="becke", becke_radius=rad)
+    ctx = XcContext(mol.coords, mk, basis, grid)
+    try:
+        ctx.build_grid()
+        xyzw, idx = ctx.export_grid()
+    finally:
+        ctx.close()
+    pts, wq, par = oracle.molecular_grid(mol.coords, mk, 4, ang, atom_mask=mask)
+    wo = oracle.becke_weights(pts, wq, par, mol.coords, rad)
+    full = np.zeros_like(wo)
+    full[idx] = xyzw[:, 3]
+    say(f"  kept {len(idx)} of {len(wo)}, max |dw|/w_q {np.max(np.abs(full - wo) / wq):.2e}")
+    assert np.all(np.abs(full - wo) <= 1e-13 * wq)
+
+
 def test_becke_cluster_parity():
     w = cfg_water_cluster(8, functional="pbe", n_rad=30, n_ang=110)
     _check(w, "pbe", partition="becke", becke_radius=w.becke_radius)

@@ -103,16 +103,18 @@ def cfg_water(functional="lda", n_rad=75, n_ang=302, seed=1, polarisation=False,
 
 
 def cfg_water_cluster(n_waters=64, functional="pbe", n_rad=100, n_ang=590,
-                      seed=2, n_occ=None, box=None):
+                      seed=2, n_occ=None, box=None, polarisation=False, pure=False):
     """n_waters rigid waters in a box (25 bohr for 64, scaled with the cube
-    root of the count otherwise), minimum O-O distance 5 bohr."""
+    root of the count otherwise), minimum O-O distance 5 bohr. polarisation
+    and pure as for cfg_water (f on O, d on H; spherical d and f shells)."""
     if box is None:
         box = 25.0 * (n_waters / 64.0) ** (1.0 / 3.0)
     if n_occ is None:
         n_occ = 4 * n_waters
     mol = water_cluster(n_waters, box=box, seed=seed)
-    return _finish(f"water{n_waters}", mol, n_occ, n_rad, n_ang, functional,
-                   seed)
+    name = f"water{n_waters}" + ("_fd" if polarisation else "") + ("_sph" if pure else "")
+    return _finish(name, mol, n_occ, n_rad, n_ang, functional, seed,
+                   polarisation=polarisation, pure=pure)
 
 
 def cfg_chain(n_atoms=600, functional="pbe", n_rad=99, n_ang=590, seed=4):

@@ -337,10 +337,14 @@ int xc_context_integrate_noalloc(xc_context* ctx, int functional, int precision,
  *  cached_bytes  persistent data plus the scratch of all batches at once:
  *                a one-wave plan, which also lets xc_context_set_phi_cache
  *                keep Phi
- * Exact once the grid is built. Before that only min_bytes is given, as an
- * estimate from the nominal grid size (build temporaries included) with one
- * batch bounded by the whole basis; cached_bytes is then 0 (it depends on
- * the screening). Either pointer may be NULL. No device work.
+ * Exact once the grid is built, for restricted LDA/GGA integrations: the
+ * spin-unrestricted and meta-GGA entry points re-plan the waves with more
+ * scratch per batch (a second set of partials; three gradient slabs and
+ * three sets of partials) and are not covered. Before the build only
+ * min_bytes is given, as an estimate from the nominal grid size (build
+ * temporaries included) with one batch bounded by the whole basis;
+ * cached_bytes is then 0 (it depends on the screening). Either pointer may
+ * be NULL. No device work.
  */
 int xc_context_footprint(xc_context* ctx, size_t* min_bytes, size_t* cached_bytes);
 

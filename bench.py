@@ -139,6 +139,12 @@ def roofline(st, timing, steps, w, functional):
     launches = timing[dom]["launches"] / steps
     achieved = flops[dom] / (phase_ms[dom] * 1e-3) / 1e12
     kname, ksrc = PHASE_KERNEL[dom]
+    if dom == "density" and st["n_wide_waves"] > 0:
+        # waves with a large work-weighted mean n_b run the 64 x 128 FP64
+        # tiles; with both kinds in the plan the per-launch figures average
+        # over the launches of both kernels
+        kname = ("k_gemm_rho_wide" if st["n_wide_waves"] == st["n_waves"]
+                 else "k_gemm_rho_wide+k_gemm_rho")
     sha = source_sha256(ksrc)
     traffic, tsrc = profiled_traffic(kname, workload_key, sha)
     return {"bound": "mfma", "kernel": kname, "phase": dom, "achieved": achieved,
@@ -234,6 +240,7 @@ def fp64_section(w, functional, steps, warmup, wave_gb, batch_merge, singles, wa
                       "n_points_kept": st["n_points"], "n_batches": st["n_batches"],
                       "mean_nb_point_weighted": st["sum_nb_ng"] / max(st["n_points"], 1),
                       "max_nb": st["max_nb"], "n_waves": st["n_waves"],
+                      "waves_with_64x128_density_tiles": st["n_wide_waves"],
                       "precision": "fp64", "parallelism": "single GPU",
                       "batch_merge": batch_merge,
                       "step": "grid build + weights + batching + screening + integration"},

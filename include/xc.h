@@ -201,6 +201,9 @@ typedef struct xc_stats {
     int built;                   /* 1 once xc_context_build_grid has run */
     size_t persistent_bytes;     /* device bytes held between integrations */
     size_t wave_bytes;           /* device scratch bytes of the largest wave */
+    int n_wide_waves;            /* waves whose FP64 density tiles are 64 x 128 (their
+                                    work-weighted mean n_b, sum n_b^2 n_g / sum n_b n_g,
+                                    is at least 512); the others use 64 x 64 */
 } xc_stats;
 
 /*

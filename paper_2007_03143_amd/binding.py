@@ -71,7 +71,8 @@ class XcStats(Structure):
                 ("n_func_entries", c_longlong), ("max_nb", c_int), ("max_ng", c_int),
                 ("sum_nb_ng", c_double), ("sum_nb2_ng", c_double),
                 ("flops_contract", c_double), ("n_waves", c_int), ("built", c_int),
-                ("persistent_bytes", c_size_t), ("wave_bytes", c_size_t)]
+                ("persistent_bytes", c_size_t), ("wave_bytes", c_size_t),
+                ("n_wide_waves", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

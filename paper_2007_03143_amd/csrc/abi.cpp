@@ -123,7 +123,7 @@ size_t device_bytes(const xc_context* c) {
                             &c->child_count, &c->child_begin, &c->batches, &c->counters,
                             &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
-                            &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch,
+                            &c->d_gemm_pre, &c->d_syr_pre, &c->d_wide_pre, &c->d_tmap, &c->scratch,
                             &c->epart, &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta,
                             &c->d_wb_meta};
     size_t n = 0;
@@ -238,7 +238,7 @@ static void release_all(xc_context* c) {
                       &c->child_count, &c->child_begin, &c->batches, &c->counters,
                       &c->scr_nsh, &c->scr_nfn, &c->scr_shoff, &c->scr_fnoff,
                       &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
-                      &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->scratch, &c->epart,
+                      &c->d_gemm_pre, &c->d_syr_pre, &c->d_wide_pre, &c->d_tmap, &c->scratch, &c->epart,
                       &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta, &c->d_wb_meta};
     for (DevBuf* b : bufs) dev_release(*b);
 }
@@ -250,7 +250,7 @@ static int plan_waves(xc_context* c) {
     c->phi_cached_kind = 0;
     c->waves.clear();
     c->h_wb.clear();
-    std::vector<int> gpre, spre;
+    std::vector<int> gpre, spre, wpre;
     c->max_nb = c->max_ng = 0;
     c->sum_nb_ng = c->sum_nb2_ng = c->flops_contract = 0.0;
     size_t budget = c->wave_budget;
@@ -265,8 +265,12 @@ static int plan_waves(xc_context* c) {
     size_t used = 0;
     gpre.push_back(0);
     spre.push_back(0);
+    wpre.push_back(0);
+    double s2 = 0.0, s1 = 0.0;   // the open wave's sum n_b^2 n_g and sum n_b n_g
     auto close_wave = [&]() {
         if (cur.count == 0) return;
+        cur.wide = s2 >= kWideNb * s1;
+        s2 = s1 = 0.0;
         c->waves.push_back(cur);
         c->max_wave_bytes = std::max(c->max_wave_bytes, used);
         Wave nx{};
@@ -277,6 +281,7 @@ static int plan_waves(xc_context* c) {
         used = 0;
         gpre.push_back(0);
         spre.push_back(0);
+        wpre.push_back(0);
     };
     c->max_wave_bytes = 0;
     for (long long j = 0; j < c->n_batches; ++j) {
@@ -310,16 +315,21 @@ static int plan_waves(xc_context* c) {
         used += bytes;
         const int gt = nmt * (ngp / kTile);
         const int st = nmt * (nmt + 1) / 2;
+        const int pt = batch_wide_tiles(w);
         gpre.push_back(gpre.back() + gt);
         spre.push_back(spre.back() + st);
+        wpre.push_back(wpre.back() + pt);
         cur.gemm_tiles += gt;
         cur.syr_tiles += st;
+        cur.wide_tiles += pt;
         cur.count += 1;
         cur.scratch_bytes = used;
         c->max_nb = std::max(c->max_nb, nb);
         c->max_ng = std::max(c->max_ng, ng);
         c->sum_nb_ng += (double)nb * ng;
         c->sum_nb2_ng += (double)nb * nb * ng;
+        s1 += (double)nb * ng;
+        s2 += (double)nb * nb * ng;
         c->flops_contract += 2.0 * nb * nb * ng + 2.0 * nb * (nb + 1.0) * ng;
     }
     close_wave();
@@ -353,6 +363,7 @@ static int plan_waves(xc_context* c) {
     }
     XC_TRY(upload(c->d_gemm_pre, gpre.data(), sizeof(int) * gpre.size(), c->stream));
     XC_TRY(upload(c->d_syr_pre, spre.data(), sizeof(int) * spre.size(), c->stream));
+    XC_TRY(upload(c->d_wide_pre, wpre.data(), sizeof(int) * wpre.size(), c->stream));
     int max_tiles = 1;
     for (const Wave& w : c->waves) max_tiles = std::max({max_tiles, w.gemm_tiles, w.syr_tiles});
     c->max_tiles = max_tiles;
@@ -596,12 +607,14 @@ int xc_context_stats(xc_context* c, xc_stats* s) {
     s->sum_nb2_ng = c->sum_nb2_ng;
     s->flops_contract = c->flops_contract;
     s->n_waves = (int)c->waves.size();
+    s->n_wide_waves = 0;
+    for (const Wave& w : c->waves) s->n_wide_waves += w.wide ? 1 : 0;
     size_t pers = 0;
     const DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells,
                             &c->d_palpha, &c->d_pcoef, &c->d_ang, &c->d_gatoms,
                             &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->d_becke_a, &c->px, &c->py, &c->pz, &c->pw, &c->pidx, &c->batches,
                             &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
-                            &c->d_gemm_pre, &c->d_syr_pre, &c->d_tmap, &c->epart,
+                            &c->d_gemm_pre, &c->d_syr_pre, &c->d_wide_pre, &c->d_tmap, &c->epart,
                             &c->npart, &c->d_req};
     for (const DevBuf* b : bufs) pers += b->cap;
     s->persistent_bytes = pers;
@@ -634,9 +647,10 @@ int xc_context_footprint(xc_context* c, size_t* min_bytes, size_t* cached_bytes)
             st_all += (long long)w.nmt * (w.nmt + 1) / 2;
         }
         const size_t nbat = c->h_wb.size();
-        // two prefix arrays of 1 + batches + waves ints each
-        const size_t pre_each = 2 * sizeof(int) * (1 + 2 * nbat);
-        const size_t pre_one = 2 * sizeof(int) * (nbat ? nbat + 2 : 1);
+        // three prefix arrays (64 x 64 and 64 x 128 GEMM tiles, SYR2K tiles) of
+        // 1 + batches + waves ints each
+        const size_t pre_each = 3 * sizeof(int) * (1 + 2 * nbat);
+        const size_t pre_one = 3 * sizeof(int) * (nbat ? nbat + 2 : 1);
         mn = core + pre_each + big + 8 * (size_t)tiles_big;
         all = core + pre_one + sum + 8 * (size_t)std::max<long long>(1, std::max(gt_all, st_all));
     } else {

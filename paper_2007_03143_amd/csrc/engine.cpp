@@ -72,7 +72,7 @@ struct xc_engine {
     size_t wave_bytes = 0;
     size_t used = 0;
     bool cache_phi = false;
-    xc::DevBuf scratch, d_wb, d_gpre, d_spre, d_reqs, d_tmap;
+    xc::DevBuf scratch, d_wb, d_gpre, d_spre, d_wpre, d_reqs, d_tmap;
     std::map<long long, xc::Request*> reqs;
     std::deque<long long> waiting;
     std::map<long long, xc::Integration*> tickets;
@@ -213,10 +213,11 @@ static void destroy_request(xc_engine* e, Request* r) {
 
 struct Group {
     std::vector<WaveBatch> wb;
-    std::vector<int> gpre{0}, spre{0};
+    std::vector<int> gpre{0}, spre{0}, wpre{0};
     std::vector<ReqDev> rd;
     std::map<Integration*, int> slot;
-    int gemm = 0, syr = 0;
+    int gemm = 0, syr = 0, wide = 0;
+    double s2 = 0.0, s1 = 0.0;   // sum n_b^2 n_g and sum n_b n_g of the group's batches
     bool sph = false;   // some request of the group has spherical shells
 };
 
@@ -294,11 +295,16 @@ static int engine_step(xc_engine* e, int* launched) {
             used += bytes;
             const int gt = w.nmt * (w.ngp / kTile);
             const int st = w.nmt * (w.nmt + 1) / 2;
+            const int pt = batch_wide_tiles(w);
             g.wb.push_back(w);
             g.gpre.push_back(g.gpre.back() + gt);
             g.spre.push_back(g.spre.back() + st);
+            g.wpre.push_back(g.wpre.back() + pt);
             g.gemm += gt;
             g.syr += st;
+            g.wide += pt;
+            g.s1 += (double)w.nb * w.ng;
+            g.s2 += (double)w.nb * w.nb * w.ng;
             in->next_batch += 1;
             *launched += 1;
             progress = true;
@@ -306,7 +312,7 @@ static int engine_step(xc_engine* e, int* launched) {
     }
     // upload the descriptors of every group (one array each, groups back to back)
     std::vector<WaveBatch> all_wb;
-    std::vector<int> all_g, all_s;
+    std::vector<int> all_g, all_s, all_p;
     std::vector<ReqDev> all_rd;
     struct Off { size_t wb, pre, rd; };
     std::map<int, Off> offs;
@@ -318,6 +324,7 @@ static int engine_step(xc_engine* e, int* launched) {
         all_wb.insert(all_wb.end(), g.wb.begin(), g.wb.end());
         all_g.insert(all_g.end(), g.gpre.begin(), g.gpre.end());
         all_s.insert(all_s.end(), g.spre.begin(), g.spre.end());
+        all_p.insert(all_p.end(), g.wpre.begin(), g.wpre.end());
         all_rd.insert(all_rd.end(), g.rd.begin(), g.rd.end());
     }
     if (!all_wb.empty()) {
@@ -325,11 +332,12 @@ static int engine_step(xc_engine* e, int* launched) {
         // read it finish first
         int max_tiles = 1;
         for (const auto& kv : groups) max_tiles = std::max({max_tiles, kv.second.gemm, kv.second.syr});
-        const size_t need[5] = {sizeof(WaveBatch) * all_wb.size(), sizeof(int) * all_g.size(),
+        const size_t need[6] = {sizeof(WaveBatch) * all_wb.size(), sizeof(int) * all_g.size(),
                                 sizeof(int) * all_s.size(), sizeof(ReqDev) * all_rd.size(),
-                                2 * sizeof(int) * (size_t)max_tiles};
-        const DevBuf* bufs[5] = {&e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs, &e->d_tmap};
-        for (int q = 0; q < 5; ++q) {
+                                2 * sizeof(int) * (size_t)max_tiles, sizeof(int) * all_p.size()};
+        const DevBuf* bufs[6] = {&e->d_wb,   &e->d_gpre, &e->d_spre,
+                                 &e->d_reqs, &e->d_tmap, &e->d_wpre};
+        for (int q = 0; q < 6; ++q) {
             if (bufs[q]->cap < need[q]) {
                 XC_HIP(hipStreamSynchronize(e->stream));
                 break;
@@ -340,9 +348,11 @@ static int engine_step(xc_engine* e, int* launched) {
         XC_TRY(dev_reserve(e->d_spre, 2 * need[2]));
         XC_TRY(dev_reserve(e->d_reqs, 2 * need[3]));
         XC_TRY(dev_reserve(e->d_tmap, 2 * need[4]));
+        XC_TRY(dev_reserve(e->d_wpre, 2 * need[5]));
         XC_TRY(upload(e->d_wb, all_wb.data(), sizeof(WaveBatch) * all_wb.size(), e->stream));
         XC_TRY(upload(e->d_gpre, all_g.data(), sizeof(int) * all_g.size(), e->stream));
         XC_TRY(upload(e->d_spre, all_s.data(), sizeof(int) * all_s.size(), e->stream));
+        XC_TRY(upload(e->d_wpre, all_p.data(), sizeof(int) * all_p.size(), e->stream));
         XC_TRY(upload(e->d_reqs, all_rd.data(), sizeof(ReqDev) * all_rd.size(), e->stream));
         for (auto& kv : groups) {
             const Group& g = kv.second;
@@ -352,8 +362,10 @@ static int engine_step(xc_engine* e, int* launched) {
             XC_TRY(launch_wave(&e->timer, e->stream, gga, precision,
                                (const WaveBatch*)e->d_wb.p + o.wb,
                                (const int*)e->d_gpre.p + o.pre,
-                               (const int*)e->d_spre.p + o.pre, (int)g.wb.size(), g.gemm,
-                               g.syr, (const ReqDev*)e->d_reqs.p, (char*)e->scratch.p,
+                               (const int*)e->d_spre.p + o.pre,
+                               (const int*)e->d_wpre.p + o.pre, (int)g.wb.size(), g.gemm,
+                               g.syr, g.wide, g.s2 >= kWideNb * g.s1,
+                               (const ReqDev*)e->d_reqs.p, (char*)e->scratch.p,
                                (int*)e->d_tmap.p, true, g.sph));
         }
         e->batches_launched += *launched;
@@ -575,7 +587,8 @@ int xc_engine_destroy(xc_engine* e) {
         destroy_request(e, kv.second);
         delete kv.second;
     }
-    DevBuf* bufs[] = {&e->scratch, &e->d_wb, &e->d_gpre, &e->d_spre, &e->d_reqs, &e->d_tmap};
+    DevBuf* bufs[] = {&e->scratch, &e->d_wb,   &e->d_gpre, &e->d_spre,
+                      &e->d_wpre,  &e->d_reqs, &e->d_tmap};
     for (DevBuf* b : bufs) dev_release(*b);
     delete e;
     return XC_OK;

@@ -569,13 +569,15 @@ __device__ inline void rho_epilogue(const WaveBatch& B, const ReqG& R, int m0, i
 }
 
 // ------------------------------------------------------- density (GEMM) ----
-// Tile of 64 functions x 64 points of X = P^j Phi^j; 4 waves, each a 32 x 32
-// block of 2 x 2 MFMA 16x16x4 tiles. A operand rows are gathered from the
+// Tile of 64 functions x 64 NW points of X = P^j Phi^j; 4 waves, each a
+// 32 x 32 NW block of 2 x 2 NW MFMA 16x16x4 tiles (NW = 2 for FP64: twice
+// the MFMAs per barrier and per A fragment read, and the A operand, a
+// gather from P, loaded once per 128 points). A operand rows are gathered from the
 // full P through the batch's function list. The epilogue (rho_epilogue)
 // spills X to LDS and reduces phi*X (grad phi * X) into per-row-tile
 // partials part[mt][q][point], q = rho, dx, dy, dz.
-template <bool GGA, typename T>
-__global__ __launch_bounds__(256) void k_gemm_rho(
+template <bool GGA, typename T, int NW>
+__device__ __forceinline__ void gemm_rho_tile(
     const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
     const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
     using M = Mfma<T>;
@@ -588,14 +590,16 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     const int nbf = R.nbf;
     const gptr<const int> func_list = R.func_list;
     const int lt = tb.y;
-    const int ntn = B.ngp / kTile;
+    constexpr int NC = kTile * NW;   // points per tile
+    const int ntn = NW == 1 ? B.ngp / kTile : (B.ngp + NC - 1) / NC;
     const int mt = lt / ntn, nt = lt - mt * ntn;
-    const int m0 = mt * kTile, n0 = nt * kTile;
+    const int m0 = mt * kTile, n0 = nt * NC;
+    const int ncol = min(NC, B.ngp - n0);   // a multiple of 64
     exp_table_init();
     const T* Phi = (const T*)phi_slab(B, R, scratch);
     const gptr<const int> fl = func_list + B.func_off;
-    // the epilogue's point (one per lane), loaded now so that its latency hides
-    const bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
+    // the first epilogue point (one per lane), loaded now so that its latency hides
+    bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
     double ex = 0.0, ey = 0.0, ez = 0.0;
     if (has) {
         const long long pi = B.pt_off + n0 + (threadIdx.x & 63);
@@ -606,12 +610,12 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
 
     // operand tiles during the main loop, the X tile in the epilogue
     constexpr int kABytes = 2 * kTile * 17 * (int)sizeof(T);
-    constexpr int kBBytes = 2 * 16 * (kTile + 1) * (int)sizeof(T);
+    constexpr int kBBytes = 2 * 16 * (NC + 1) * (int)sizeof(T);
     constexpr int kXBytes = kTile * (kTile + 1) * 8;
     constexpr int kLds = (kABytes + kBBytes > kXBytes) ? kABytes + kBBytes : kXBytes;
     __shared__ __attribute__((aligned(16))) char lds[kLds];
     T (*As)[kTile][17] = reinterpret_cast<T (*)[kTile][17]>(lds);
-    T (*Bs)[16][kTile + 1] = reinterpret_cast<T (*)[16][kTile + 1]>(lds + kABytes);
+    T (*Bs)[16][NC + 1] = reinterpret_cast<T (*)[16][NC + 1]>(lds + kABytes);
     double (*Xs)[kTile + 1] = reinterpret_cast<double (*)[kTile + 1]>(lds);
     __shared__ int frow[kTile], fsh[kTile];
     // function indices (columns of P) of four consecutive K steps
@@ -645,7 +649,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     __syncthreads();
 
     const int ar = tid >> 2, ac = (tid & 3) * 4;
-    const int br = tid >> 4, bc = (tid & 15) * 4;
+    const int br = tid >> 4, bc = (tid & 15) * 4;   // B columns bc + 64 w, w < NW
     const int fr = frow[ar];
     const gptr<const double> Prow = P + (size_t)(fr >= 0 ? fr : 0) * nbf;
 
@@ -655,7 +659,7 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
     // values stay FP64 until the LDS store, where they are rounded and the
     // padding is selected away, all loads going to valid (clamped) addresses.
     struct Regs {
-        T ra[4], rb[4];
+        T ra[4], rb[4 * NW];
         double pv[4];
         int fc[4];
     };
@@ -678,7 +682,11 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         }
         const T* src = Phi + (size_t)(ks * 16 + br) * B.ngp + n0 + bc;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) r.rb[q] = src[q];
+        for (int w = 0; w < NW; ++w)
+            if (w == 0 || w * kTile < ncol) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r.rb[4 * w + q] = src[kTile * w + q];
+            }
     };
     auto sstore = [&](Regs& r, int buf) {
         if constexpr (sizeof(T) == 4) {
@@ -691,22 +699,30 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
             As[buf][ar][ac + q] = r.ra[q];
             Bs[buf][br][bc + q] = r.rb[q];
         }
+#pragma unroll
+        for (int w = 1; w < NW; ++w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Bs[buf][br][kTile * w + bc + q] = r.rb[4 * w + q];
     };
 
-    typename M::acc acc[2][2];
+    // the wave's output blocks: rows wm * 32 + 16 mb, columns
+    // 64 w + wn * 32 + 16 nb of the tile (block index 2 w + nb)
+    constexpr int NB = 2 * NW;
+    typename M::acc acc[2][NB];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
+        for (int j = 0; j < NB; ++j) acc[i][j] = M::zero();
+    auto bcol = [&](int nb) { return kTile * (nb >> 1) + wn * 32 + (nb & 1) * 16; };
 
     // 16 x 16 output blocks made only of padding rows or columns are skipped
     // (wave-uniform)
-    bool live[2][2];
+    bool live[2][NB];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-            live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + wn * 32 + nb * 16 < B.ng);
+        for (int nb = 0; nb < NB; ++nb)
+            live[mb][nb] = (m0 + wm * 32 + mb * 16 < B.nb) && (n0 + bcol(nb) < B.ng);
 
     fread(RA, 0);
     gload(RA, 0);
@@ -728,17 +744,17 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            T a[2], b[2];
+            T a[2], b[NB];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
                 a[mb] = As[cur][wm * 32 + mb * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-                b[nb] = Bs[cur][kk * 4 + (lane >> 4)][wn * 32 + nb * 16 + (lane & 15)];
+            for (int nb = 0; nb < NB; ++nb)
+                b[nb] = Bs[cur][kk * 4 + (lane >> 4)][bcol(nb) + (lane & 15)];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb)
+                for (int nb = 0; nb < NB; ++nb)
                     if (live[mb][nb]) acc[mb][nb] = M::mma(a[mb], b[nb], acc[mb][nb]);
         }
         if (ks + 1 < nk) sstore(rs, cur ^ 1);
@@ -753,18 +769,48 @@ __global__ __launch_bounds__(256) void k_gemm_rho(
         if (ks + 1 < nk) step(ks + 1, RB, RA);
     }
 
-    // spill X (the loop ended on a barrier, so the operand tiles are free)
+    // X by 64-point halves: spill, then the epilogue (the loop ended on a
+    // barrier, so the operand tiles are free)
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int w = 0; w < NW; ++w) {
+        if (w > 0 && w * kTile >= ncol) break;
+        if (w > 0) {
+            has = n0 + kTile * w + (int)(threadIdx.x & 63) < B.ng;
+            if (has) {
+                const long long pi = B.pt_off + n0 + kTile * w + (threadIdx.x & 63);
+                ex = R.px[pi];
+                ey = R.py[pi];
+                ez = R.pz[pi];
+            }
+            __syncthreads();   // the previous half's epilogue is done with Xs
+        }
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                Xs[wm * 32 + mb * 16 + M::acc_row(r, lane)][wn * 32 + nb * 16 + (lane & 15)] =
-                    double(acc[mb][nb][r]);
-    __syncthreads();
+            for (int nb = 2 * w; nb < 2 * w + 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Xs[wm * 32 + mb * 16 + M::acc_row(r, lane)][wn * 32 + (nb & 1) * 16 + (lane & 15)] =
+                        double(acc[mb][nb][r]);
+        __syncthreads();
+        rho_epilogue<GGA>(B, R, m0, n0 + kTile * w, mt, Xs, fsh, frow, ex, ey, ez, has, scratch);
+    }
+}
 
-    rho_epilogue<GGA>(B, R, m0, n0, mt, Xs, fsh, frow, ex, ey, ez, has, scratch);
+// 64 x 64 tiles (FP64 and FP32), four workgroups per CU.
+template <bool GGA, typename T>
+__global__ __launch_bounds__(256) void k_gemm_rho(
+    const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
+    const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
+    gemm_rho_tile<GGA, T, 1>(wb, tmap, ntiles, reqs, scratch);
+}
+
+// 64 x 128 tiles (FP64), three workgroups per CU.
+template <bool GGA>
+__global__ __launch_bounds__(256, 3) void k_gemm_rho_wide(
+    const WaveBatch* __restrict__ wb, const int2* __restrict__ tmap, int ntiles,
+    const ReqDev* __restrict__ reqs, char* __restrict__ scratch) {
+    gemm_rho_tile<GGA, double, 2>(wb, tmap, ntiles, reqs, scratch);
 }
 
 // ------------------------------------------------- functional + Z matrix --
@@ -1798,19 +1844,45 @@ __global__ void k_reduce_en(const double* epart, const double* npart, long long 
 }
 
 // ------------------------------------------------------------- driver -----
+// FP64 density contraction of one wave's batches: 64 x 128 tiles when the
+// wave's work-weighted mean n_b is large (wide; the long K loops amortise
+// the lower occupancy), else 64 x 64 tiles.
+template <bool GGA>
+static int launch_density_fp64(hipStream_t s, const WaveBatch* b, const int* gpre,
+                               const int* wpre, int count, int gemm_tiles, int wide_tiles,
+                               bool wide, const ReqDev* reqs, char* scr, int2* tmap) {
+    const int n = wide ? wide_tiles : gemm_tiles;
+    if (n <= 0) return XC_OK;
+    hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, wide ? wpre : gpre,
+                       count, tmap);
+    XC_HIP(hipGetLastError());
+    if (wide)
+        hipLaunchKernelGGL((k_gemm_rho_wide<GGA>), dim3(n), dim3(256), 0, s, b,
+                           (const int2*)tmap, n, reqs, scr);
+    else
+        hipLaunchKernelGGL((k_gemm_rho<GGA, double>), dim3(n), dim3(256), 0, s, b,
+                           (const int2*)tmap, n, reqs, scr);
+    XC_HIP(hipGetLastError());
+    return XC_OK;
+}
+
 // T: storage of Phi and arithmetic of the density contraction; TZ: storage
 // of Z and arithmetic of the potential contraction.
 template <bool GGA, typename T, typename TZ>
 static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
-                         const int* gpre, const int* spre, int count, int gemm_tiles,
-                         int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
-                         bool colloc, bool sph) {
+                         const int* gpre, const int* spre, const int* wpre, int count,
+                         int gemm_tiles, int syr_tiles, int wide_tiles, bool wide,
+                         const ReqDev* reqs, char* scr, int2* tmap, bool colloc, bool sph) {
     if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
         hipLaunchKernelGGL((k_colloc<T, false>), dim3(count), dim3(256), 0, s, b, reqs, scr);
         XC_HIP(hipGetLastError());
     }
-    if (gemm_tiles > 0) {
+    if constexpr (sizeof(T) == 8) {
+        PhaseScope ps(timer, s, XC_PHASE_DENSITY);
+        XC_TRY(launch_density_fp64<GGA>(s, b, gpre, wpre, count, gemm_tiles, wide_tiles, wide,
+                                        reqs, scr, tmap));
+    } else if (gemm_tiles > 0) {
         PhaseScope ps(timer, s, XC_PHASE_DENSITY);
         hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, gpre, count,
                            tmap);
@@ -1843,9 +1915,9 @@ static int launch_wave_t(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
 // FP32, both contractions on BF16 MFMA.
 template <bool GGA>
 static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b,
-                            const int* gpre, const int* spre, int count, int gemm_tiles,
-                            int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
-                            bool colloc, bool sph) {
+                            const int* gpre, const int* spre, const int* /*wpre*/, int count,
+                            int gemm_tiles, int syr_tiles, int /*wide_tiles*/, bool /*wide*/,
+                            const ReqDev* reqs, char* scr, int2* tmap, bool colloc, bool sph) {
     if (colloc) {
         PhaseScope ps(timer, s, XC_PHASE_COLLOC);
         hipLaunchKernelGGL((k_colloc<double, true>), dim3(count), dim3(256), 0, s, b, reqs, scr);
@@ -1881,13 +1953,13 @@ static int launch_wave_bf16(PhaseTimer* timer, hipStream_t s, const WaveBatch* b
 }
 
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
-                const WaveBatch* d_wb, const int* d_gpre, const int* d_spre, int count,
-                int gemm_tiles, int syr_tiles, const ReqDev* d_reqs, char* scratch,
-                int* d_tmap_i, bool colloc, bool sph) {
+                const WaveBatch* d_wb, const int* d_gpre, const int* d_spre, const int* d_wpre,
+                int count, int gemm_tiles, int syr_tiles, int wide_tiles, bool wide,
+                const ReqDev* d_reqs, char* scratch, int* d_tmap_i, bool colloc, bool sph) {
     if (count == 0) return XC_OK;
     int2* t = (int2*)d_tmap_i;
-#define XC_WAVE_ARGS timer, s, d_wb, d_gpre, d_spre, count, gemm_tiles, syr_tiles, d_reqs, \
-                     scratch, t, colloc, sph
+#define XC_WAVE_ARGS timer, s, d_wb, d_gpre, d_spre, d_wpre, count, gemm_tiles, syr_tiles, \
+                     wide_tiles, wide, d_reqs, scratch, t, colloc, sph
     if (precision == XC_MIXED_FP32)
         return gga ? launch_wave_t<true, float, float>(XC_WAVE_ARGS)
                    : launch_wave_t<false, float, float>(XC_WAVE_ARGS);
@@ -1907,21 +1979,14 @@ int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
 // and the potential contraction for each spin in turn (the Z slab is reused).
 template <bool GGA>
 static int launch_wave_uks_t(hipStream_t s, const WaveBatch* wa, const WaveBatch* wbb,
-                             const int* gpre, const int* spre, int count, int gemm_tiles,
-                             int syr_tiles, const ReqDev* reqs, char* scr, int2* tmap,
-                             bool sph) {
+                             const Wave& wv, const int* gpre, const int* wpre, const int* spre,
+                             const ReqDev* reqs, char* scr, int2* tmap, bool sph) {
+    const int count = wv.count, syr_tiles = wv.syr_tiles;
     hipLaunchKernelGGL((k_colloc<double, false>), dim3(count), dim3(256), 0, s, wa, reqs, scr);
     XC_HIP(hipGetLastError());
-    if (gemm_tiles > 0) {
-        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, gpre, count,
-                           tmap);
-        XC_HIP(hipGetLastError());
-        for (const WaveBatch* w : {wa, wbb}) {
-            hipLaunchKernelGGL((k_gemm_rho<GGA, double>), dim3(gemm_tiles), dim3(256), 0, s, w,
-                               (const int2*)tmap, gemm_tiles, reqs, scr);
-            XC_HIP(hipGetLastError());
-        }
-    }
+    for (const WaveBatch* w : {wa, wbb})
+        XC_TRY(launch_density_fp64<GGA>(s, w, gpre, wpre, count, wv.gemm_tiles, wv.wide_tiles,
+                                        wv.wide, reqs, scr, tmap));
     hipLaunchKernelGGL((k_func_spin<GGA>), dim3(count), dim3(256), 0, s, wa, reqs, scr);
     XC_HIP(hipGetLastError());
     if (syr_tiles > 0) {
@@ -1956,13 +2021,13 @@ int run_integrate_uks(xc_context* c, int functional, const double* dPa, const do
     const WaveBatch* wa = (const WaveBatch*)c->d_wb.p;
     const WaveBatch* wbb = (const WaveBatch*)c->d_wb_beta.p;
     const int* gpre = (const int*)c->d_gemm_pre.p;
+    const int* wpre = (const int*)c->d_wide_pre.p;
     const int* spre = (const int*)c->d_syr_pre.p;
     for (const Wave& w : c->waves) {
         if (w.count == 0) continue;
         XC_TRY((gga ? launch_wave_uks_t<true> : launch_wave_uks_t<false>)(
-            c->stream, wa + w.wb_off, wbb + w.wb_off, gpre + w.pre_off, spre + w.pre_off, w.count,
-            w.gemm_tiles, w.syr_tiles, d_req, (char*)c->scratch.p, (int2*)c->d_tmap.p,
-            c->any_pure));
+            c->stream, wa + w.wb_off, wbb + w.wb_off, w, gpre + w.pre_off, wpre + w.pre_off,
+            spre + w.pre_off, d_req, (char*)c->scratch.p, (int2*)c->d_tmap.p, c->any_pure));
     }
     XC_TRY(launch_finish(nullptr, c->stream, dVb, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN));
@@ -1978,25 +2043,19 @@ int run_integrate_uks(xc_context* c, int functional, const double* dPa, const do
 // contraction with Phi, and Z_d = c d phi/dd with the potential contraction
 // against gradient slab d, for d = x, y, z (the Z slab is reused).
 static int launch_wave_meta(hipStream_t s, const WaveBatch* wb, const WaveBatch* wm,
-                            long long n_all, const int* gpre, const int* spre, int count,
-                            int gemm_tiles, int syr_tiles, const ReqDev* reqs, char* scr,
-                            int2* tmap, bool sph) {
+                            long long n_all, const Wave& wv, const int* gpre, const int* wpre,
+                            const int* spre, const ReqDev* reqs, char* scr, int2* tmap,
+                            bool sph) {
+    const int count = wv.count, syr_tiles = wv.syr_tiles;
     hipLaunchKernelGGL((k_colloc<double, false>), dim3(count), dim3(256), 0, s, wb, reqs, scr);
     XC_HIP(hipGetLastError());
     if (sph) hipLaunchKernelGGL(k_grad<true>, dim3(count), dim3(256), 0, s, wb, reqs, scr);
     else hipLaunchKernelGGL(k_grad<false>, dim3(count), dim3(256), 0, s, wb, reqs, scr);
     XC_HIP(hipGetLastError());
     const WaveBatch* sets[4] = {wb, wm, wm + n_all, wm + 2 * n_all};
-    if (gemm_tiles > 0) {
-        hipLaunchKernelGGL(k_tile_map, dim3(grid_1d(count, 256)), dim3(256), 0, s, gpre, count,
-                           tmap);
-        XC_HIP(hipGetLastError());
-        for (const WaveBatch* w : sets) {
-            hipLaunchKernelGGL((k_gemm_rho<true, double>), dim3(gemm_tiles), dim3(256), 0, s, w,
-                               (const int2*)tmap, gemm_tiles, reqs, scr);
-            XC_HIP(hipGetLastError());
-        }
-    }
+    for (const WaveBatch* w : sets)
+        XC_TRY(launch_density_fp64<true>(s, w, gpre, wpre, count, wv.gemm_tiles, wv.wide_tiles,
+                                         wv.wide, reqs, scr, tmap));
     hipLaunchKernelGGL(k_func_meta, dim3(count), dim3(256), 0, s, wb, reqs, scr);
     XC_HIP(hipGetLastError());
     if (syr_tiles > 0) {
@@ -2027,11 +2086,12 @@ int run_integrate_meta(xc_context* c, const double* dP, double* dV, double* dEN)
     const WaveBatch* wm = (const WaveBatch*)c->d_wb_meta.p;
     const long long n_all = (long long)c->h_wb.size();
     const int* gpre = (const int*)c->d_gemm_pre.p;
+    const int* wpre = (const int*)c->d_wide_pre.p;
     const int* spre = (const int*)c->d_syr_pre.p;
     for (const Wave& w : c->waves) {
         if (w.count == 0) continue;
-        XC_TRY(launch_wave_meta(c->stream, wb + w.wb_off, wm + w.wb_off, n_all, gpre + w.pre_off,
-                                spre + w.pre_off, w.count, w.gemm_tiles, w.syr_tiles,
+        XC_TRY(launch_wave_meta(c->stream, wb + w.wb_off, wm + w.wb_off, n_all, w,
+                                gpre + w.pre_off, wpre + w.pre_off, spre + w.pre_off,
                                 (const ReqDev*)c->d_req.p, (char*)c->scratch.p,
                                 (int2*)c->d_tmap.p, c->any_pure));
     }
@@ -2126,6 +2186,7 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
     const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
     const int* gpre = (const int*)c->d_gemm_pre.p;
     const int* spre = (const int*)c->d_syr_pre.p;
+    const int* wpre = (const int*)c->d_wide_pre.p;
     // With one wave the scratch still holds the previous integration's Phi
     // (no later kernel writes its slab), so a cached Phi of the same storage
     // type is used as it stands.
@@ -2135,9 +2196,10 @@ int run_integrate(xc_context* c, int functional, int precision, const double* dP
     c->phi_cached_kind = 0;
     for (const Wave& w : c->waves)
         XC_TRY(launch_wave(&c->timer, c->stream, gga, precision, wb + w.wb_off,
-                           gpre + w.pre_off, spre + w.pre_off, w.count, w.gemm_tiles,
-                           w.syr_tiles, (const ReqDev*)c->d_req.p, (char*)c->scratch.p,
-                           (int*)c->d_tmap.p, colloc, c->any_pure));
+                           gpre + w.pre_off, spre + w.pre_off, wpre + w.pre_off, w.count,
+                           w.gemm_tiles, w.syr_tiles, w.wide_tiles, w.wide,
+                           (const ReqDev*)c->d_req.p, (char*)c->scratch.p, (int*)c->d_tmap.p,
+                           colloc, c->any_pure));
     if (cacheable) c->phi_cached_kind = kind;
     return launch_finish(&c->timer, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);

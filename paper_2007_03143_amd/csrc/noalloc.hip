@@ -81,10 +81,12 @@ int run_integrate_noalloc(xc_context* c, int functional, int precision, const do
     const WaveBatch* wb = (const WaveBatch*)c->d_wb.p;
     const int* gpre = (const int*)c->d_gemm_pre.p;
     const int* spre = (const int*)c->d_syr_pre.p;
+    const int* wpre = (const int*)c->d_wide_pre.p;
     for (const Wave& w : c->waves)
         XC_TRY(launch_wave(nullptr, c->stream, gga, precision, wb + w.wb_off, gpre + w.pre_off,
-                           spre + w.pre_off, w.count, w.gemm_tiles, w.syr_tiles, d_req,
-                           wave_scratch, d_tmap, true, c->any_pure));
+                           spre + w.pre_off, wpre + w.pre_off, w.count, w.gemm_tiles,
+                           w.syr_tiles, w.wide_tiles, w.wide, d_req, wave_scratch, d_tmap, true,
+                           c->any_pure));
     return launch_finish(nullptr, c->stream, dV, c->nbf, (const double*)c->epart.p,
                          (const double*)c->npart.p, c->n_batches, dEN);
 }

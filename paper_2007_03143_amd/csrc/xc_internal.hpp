@@ -139,6 +139,15 @@ __host__ __device__ inline long long scale_row_off(const WaveBatch& w) {
     return (long long)w.nbp * w.ngp;
 }
 
+// A launch of FP64 density tiles uses 64 x 128 tiles when the work-weighted
+// mean n_b of its batches, sum n_b^2 n_g / sum n_b n_g, is at least this.
+constexpr double kWideNb = 512.0;
+
+// Density tiles of a batch for the FP64 kernel: 64 rows x 128 points.
+inline int batch_wide_tiles(const WaveBatch& w) {
+    return w.nmt * ((w.ngp + 127) / 128);
+}
+
 // Larger of the batch's density-GEMM and potential-SYR2K tile counts.
 inline int batch_tiles(const WaveBatch& w) {
     const int gt = w.nmt * (w.ngp / kTile), st = w.nmt * (w.nmt + 1) / 2;
@@ -174,8 +183,10 @@ struct ReqDev {
 struct Wave {
     int first;          // first batch (global index)
     int count;          // number of batches
-    int gemm_tiles;
+    int gemm_tiles;     // 64 x 64 density tiles (FP32 and split-BF16 kernels)
     int syr_tiles;
+    int wide_tiles;     // 64 x 128 density tiles (FP64 kernel)
+    bool wide;          // FP64 density tiles of 64 x 128 (else 64 x 64)
     long long wb_off;   // offset into the WaveBatch array
     long long pre_off;  // offset into the tile-prefix arrays (count + 1 entries)
     size_t scratch_bytes;
@@ -245,7 +256,7 @@ struct xc_context {
     // wave plan
     std::vector<xc::Wave> waves;
     std::vector<xc::WaveBatch> h_wb;
-    xc::DevBuf d_wb, d_gemm_pre, d_syr_pre;
+    xc::DevBuf d_wb, d_gemm_pre, d_syr_pre, d_wide_pre;
     xc::DevBuf d_tmap;           // tile -> (batch, tile in batch) of one launch
     xc::DevBuf scratch;
     size_t max_wave_bytes = 0;
@@ -326,13 +337,17 @@ int launch_put_req(hipStream_t s, ReqDev* dst, const ReqDev& v);
 // colloc = false skips the collocation kernel: the scratch already holds Phi
 // of these batches in the storage type of this precision. sph: some batch of
 // the launch has spherical shells (selects the Z kernel that forms them).
+// wide: FP64 density tiles of 64 x 128 (d_wpre, wide_tiles), else 64 x 64
+// (d_gpre, gemm_tiles); the FP32 and split-BF16 density kernels use 64 x 64.
 int launch_wave(PhaseTimer* timer, hipStream_t s, bool gga, int precision,
                 const WaveBatch* d_wb, const int* d_gpre, const int* d_spre,
-                int count, int gemm_tiles, int syr_tiles, const ReqDev* d_reqs,
+                const int* d_wpre, int count, int gemm_tiles, int syr_tiles,
+                int wide_tiles, bool wide, const ReqDev* d_reqs,
                 char* scratch, int* d_tmap, bool colloc, bool sph);
-// Spin-unrestricted integration (FP64) of a context planned with
-// meta_plan: meta-GGA (TPSS), FP64, P in, V and (E_xc, N_e) out.
+// Meta-GGA (TPSS) integration of a context planned with meta_plan: FP64,
+// P in, V and (E_xc, N_e) out.
 int run_integrate_meta(xc_context* c, const double* dP, double* dV, double* dEN);
+// Spin-unrestricted integration (FP64) of a context planned with
 // spin_plan: P^a, P^b in, V^a, V^b and (E_xc, N_e) out.
 int run_integrate_uks(xc_context* c, int functional, const double* dPa, const double* dPb,
                       double* dVa, double* dVb, double* dEN);

@@ -39,7 +39,8 @@ def _check(w, functional, **kw):
 
 @pytest.mark.parametrize("functional", ["lda", "pbe"])
 def test_water_parity(functional):
-    _check(cfg_water(), functional)
+    E, N, V, st = _check(cfg_water(), functional)
+    assert st["n_wide_waves"] == 0    # small batches: 64 x 64 density tiles
 
 
 @pytest.mark.parametrize("functional", ["lda", "pbe"])
@@ -557,6 +558,9 @@ def test_chain600_full_grid_atoms_match_golden():
             f"({len(r)} entries) max d(row sum) {drs:.3e}; batches {st['n_batches']} "
             f"max n_b {st['max_nb']} (row tiles {(st['max_nb'] + 63) // 64})")
         assert st["max_nb"] > 2048
+        # these batches are large enough for the 64 x 128 FP64 density tiles
+        say(f"  waves {st['n_waves']}, with 64 x 128 density tiles {st['n_wide_waves']}")
+        assert st["n_wide_waves"] == st["n_waves"]
         assert abs(E - g["E_xc"]) <= TOL_E and abs(N - g["N_e"]) <= TOL_E
         assert dv <= TOL_V and drs <= TOL_V
         assert np.array_equal(V, V.T)

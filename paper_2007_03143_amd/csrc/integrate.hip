@@ -67,9 +67,11 @@ struct ReqG {
     int nbf;
 };
 
-// Start of a batch's Phi slab: the request's Phi store, or the wave scratch.
-__device__ inline char* phi_slab(const WaveBatch& B, const ReqG& R, char* scratch) {
-    return (R.phi_base ? R.phi_base : scratch) + 8 * B.phi_off;
+// Start of a batch's Phi slab: the request's Phi store, or the wave scratch
+// (both global memory; typed so, the slab's loads and stores do not become
+// flat instructions, which would also hold up every wait for LDS data).
+__device__ inline gptr<char> phi_slab(const WaveBatch& B, const ReqG& R, char* scratch) {
+    return to_global(R.phi_base ? R.phi_base : scratch) + 8 * B.phi_off;
 }
 
 __device__ inline ReqG global_view(const ReqDev& r) {
@@ -295,7 +297,7 @@ __device__ inline void z_shell(double dx, double dy, double dz, double rad, doub
 // stores the digits of value * inv (T = unsigned long long).
 template <int L, int MODE, typename T>
 __device__ inline double phi_shell_mode(const ShellDev& sh, double dx, double dy, double dz,
-                                        double rad, T* out, int ngp, double inv) {
+                                        double rad, gptr<T> out, int ngp, double inv) {
     constexpr int NC = (L + 1) * (L + 2) / 2;
     double xp[L + 1], yp[L + 1], zp[L + 1];
     xp[0] = yp[0] = zp[0] = 1.0;
@@ -345,7 +347,7 @@ __device__ inline double phi_shell_mode(const ShellDev& sh, double dx, double dy
 template <int MODE, typename T>
 __device__ inline void colloc_pass(const WaveBatch& B, const ReqG& R, const double* sx,
                                    const double* sy, const double* sz,
-                                   unsigned long long* smax, T* Phi) {
+                                   unsigned long long* smax, gptr<T> Phi) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     for (int sl = wave; sl < B.nshell; sl += 4) {
@@ -357,7 +359,7 @@ __device__ inline void colloc_pass(const WaveBatch& B, const ReqG& R, const doub
             const double r2 = dist2_nc(sx[i], sy[i], sz[i], sh, dx, dy, dz);
             if (i < B.ng) shell_radial(sh, R.palpha, R.pcoef, r2, rad, drad);
             else rad = drad = 0.0;
-            T* out = Phi + (size_t)loff * B.ngp + i;
+            const gptr<T> out = Phi + (size_t)loff * B.ngp + i;
             const double inv = MODE == 2 ? __longlong_as_double((long long)smax[i]) : 0.0;
             double mx;
             switch (sh.L) {
@@ -390,15 +392,15 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
         if (SCALE) smax[i] = 0ull;
     }
     __syncthreads();
-    char* phi = phi_slab(B, R, scratch);
+    const gptr<char> phi = phi_slab(B, R, scratch);
     // zero the padding rows n_b .. n_bp - 1 (a zero value has zero digits)
     const long long npad = (long long)(B.nbp - B.nb) * B.ngp;
     if constexpr (SCALE) {
-        unsigned long long* dig = (unsigned long long*)phi;
+        const gptr<unsigned long long> dig = (gptr<unsigned long long>)phi;
         for (long long k = threadIdx.x; k < npad; k += blockDim.x) dig[(size_t)B.nb * B.ngp + k] = 0ull;
         colloc_pass<1, unsigned long long>(B, R, sx, sy, sz, smax, dig);
         __syncthreads();
-        double* sc = (double*)phi + scale_row_off(B);
+        const gptr<double> sc = (gptr<double>)phi + scale_row_off(B);
         for (int i = threadIdx.x; i < B.ngp; i += blockDim.x) {
             const double m = __longlong_as_double((long long)smax[i]);
             int e = 0;
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(256) void k_colloc(const WaveBatch* __restrict__ wb
         __syncthreads();
         colloc_pass<2, unsigned long long>(B, R, sx, sy, sz, smax, dig);
     } else {
-        T* Phi = (T*)phi;
+        const gptr<T> Phi = (gptr<T>)phi;
         for (long long k = threadIdx.x; k < npad; k += blockDim.x) Phi[(size_t)B.nb * B.ngp + k] = T(0);
         colloc_pass<0, T>(B, R, sx, sy, sz, smax, Phi);
     }
@@ -596,7 +598,7 @@ __device__ __forceinline__ void gemm_rho_tile(
     const int m0 = mt * kTile, n0 = nt * NC;
     const int ncol = min(NC, B.ngp - n0);   // a multiple of 64
     exp_table_init();
-    const T* Phi = (const T*)phi_slab(B, R, scratch);
+    const gptr<const T> Phi = (gptr<const T>)phi_slab(B, R, scratch);
     const gptr<const int> fl = func_list + B.func_off;
     // the first epilogue point (one per lane), loaded now so that its latency hides
     bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
@@ -680,7 +682,7 @@ __device__ __forceinline__ void gemm_rho_tile(
             for (int q = 0; q < 4; ++q)
                 r.ra[q] = (fr >= 0 && r.fc[q] >= 0) ? T(Prow[r.fc[q]]) : T(0);
         }
-        const T* src = Phi + (size_t)(ks * 16 + br) * B.ngp + n0 + bc;
+        const gptr<const T> src = Phi + (size_t)(ks * 16 + br) * B.ngp + n0 + bc;
 #pragma unroll
         for (int w = 0; w < NW; ++w)
             if (w == 0 || w * kTile < ncol) {
@@ -1161,8 +1163,8 @@ __global__ __launch_bounds__(256) void k_syr2k(
     while ((I + 1) * (I + 2) / 2 <= lt) ++I;
     while (I * (I + 1) / 2 > lt) --I;
     const int J = lt - I * (I + 1) / 2;
-    const TP* Phi = (const TP*)phi_slab(B, R, (char*)scratch);
-    const T* Zm = (const T*)(scratch + 8 * B.z_off);
+    const gptr<const TP> Phi = (gptr<const TP>)phi_slab(B, R, (char*)scratch);
+    const gptr<const T> Zm = (gptr<const T>)to_global(scratch + 8 * B.z_off);
     const gptr<const int> fl = func_list + B.func_off;
 
     // K steps of 8. FP64: one LDS buffer (the next step's operands wait in
@@ -1196,10 +1198,10 @@ __global__ __launch_bounds__(256) void k_syr2k(
     T (*tPJ)[kTile][KP] = diag ? sPI : sPJ;
     T (*tZJ)[kTile][KP] = diag ? sZI : sZJ;
     const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
-    const T* zI = Zm + (size_t)(vI ? rI : 0) * B.ngp;
-    const TP* pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
-    const T* zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
-    const TP* pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
+    const gptr<const T> zI = Zm + (size_t)(vI ? rI : 0) * B.ngp;
+    const gptr<const TP> pI = Phi + (size_t)(vI ? rI : 0) * B.ngp;
+    const gptr<const T> zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
+    const gptr<const TP> pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
 
     // FP32: loads from the clamped (always valid) rows, padding rows zeroed
     // after the load, so no branch separates the loads (with a branch around
@@ -1352,6 +1354,7 @@ __global__ __launch_bounds__(256) void k_syr2k(
 // 16 lanes fall in distinct banks.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef unsigned long long v2u64 __attribute__((ext_vector_type(2)));
 constexpr int kKB = 32;        // K step of the split-BF16 kernels
 constexpr int kBP = kKB + 8;   // LDS row pitch in bf16
 
@@ -1433,9 +1436,9 @@ __global__ __launch_bounds__(256, 3) void k_gemm_rho_bf16(
     const int mt = lt / ntn, nt = lt - mt * ntn;
     const int m0 = mt * kTile, n0 = nt * kTile;
     exp_table_init();
-    const char* phi = phi_slab(B, R, scratch);
-    const unsigned long long* Phid = (const unsigned long long*)phi;
-    const double* pscale = (const double*)phi + scale_row_off(B);
+    const gptr<const char> phi = phi_slab(B, R, scratch);
+    const gptr<const unsigned long long> Phid = (gptr<const unsigned long long>)phi;
+    const gptr<const double> pscale = (gptr<const double>)phi + scale_row_off(B);
     const gptr<const int> fl = R.func_list + B.func_off;
     // the epilogue's point (one per lane), loaded now so that its latency hides
     const bool has = n0 + (int)(threadIdx.x & 63) < B.ng;
@@ -1628,10 +1631,10 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     while ((I + 1) * (I + 2) / 2 <= lt) ++I;
     while (I * (I + 1) / 2 > lt) --I;
     const int J = lt - I * (I + 1) / 2;
-    const char* phi = phi_slab(B, R, (char*)scratch);
-    const unsigned long long* Phid = (const unsigned long long*)phi;
-    const float* Zm = (const float*)(scratch + 8 * B.z_off);
-    const double* pscale = (const double*)phi + scale_row_off(B);
+    const gptr<const char> phi = phi_slab(B, R, (char*)scratch);
+    const gptr<const unsigned long long> Phid = (gptr<const unsigned long long>)phi;
+    const gptr<const float> Zm = (gptr<const float>)to_global(scratch + 8 * B.z_off);
+    const gptr<const double> pscale = (gptr<const double>)phi + scale_row_off(B);
     const gptr<const int> fl = func_list + B.func_off;
 
     // ZI, PI, PJ, ZJ, each (hi, lo): one buffer
@@ -1656,13 +1659,14 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
     const int rI = I * kTile + lr, rJ = J * kTile + lr;
     const bool vI = rI < B.nbp, vJ = rJ < B.nbp;
     // operand a: 0 = Z_I, 1 = Phi_I, 2 = Phi_J, 3 = Z_J
-    const float* zsrc[2] = {Zm + (size_t)(vI ? rI : 0) * B.ngp, Zm + (size_t)(vJ ? rJ : 0) * B.ngp};
-    const unsigned long long* psrc[2] = {Phid + (size_t)(vI ? rI : 0) * B.ngp,
+    const gptr<const float> zsrc[2] = {Zm + (size_t)(vI ? rI : 0) * B.ngp,
+                                       Zm + (size_t)(vJ ? rJ : 0) * B.ngp};
+    const gptr<const unsigned long long> psrc[2] = {Phid + (size_t)(vI ? rI : 0) * B.ngp,
                                          Phid + (size_t)(vJ ? rJ : 0) * B.ngp};
     // a diagonal tile's column operands are its row operands
     const bool diag = I == J;
-    float4 gz[2][2];
-    ulonglong2 gp[2][4];
+    v4f gz[2][2];
+    v2u64 gp[2][4];
     float sc[8];     // s_i 2^-7 of the step's eight points
     auto gload = [&](int ks) {
         const int k0 = ks * kKB + lk;
@@ -1671,14 +1675,14 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && diag) continue;
-            gz[h][0] = *reinterpret_cast<const float4*>(zsrc[h] + k0);
-            gz[h][1] = *reinterpret_cast<const float4*>(zsrc[h] + k0 + 4);
+            gz[h][0] = *reinterpret_cast<gptr<const v4f>>(zsrc[h] + k0);
+            gz[h][1] = *reinterpret_cast<gptr<const v4f>>(zsrc[h] + k0 + 4);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                gp[h][q] = *reinterpret_cast<const ulonglong2*>(psrc[h] + k0 + 2 * q);
+                gp[h][q] = *reinterpret_cast<gptr<const v2u64>>(psrc[h] + k0 + 2 * q);
         }
     };
-    auto put_z = [&](int which, const float4 (&g)[2], bool valid) {
+    auto put_z = [&](int which, const v4f (&g)[2], bool valid) {
         const float x[8] = {g[0].x, g[0].y, g[0].z, g[0].w, g[1].x, g[1].y, g[1].z, g[1].w};
         bf16x8 hv, lv;
 #pragma unroll
@@ -1691,7 +1695,7 @@ __global__ __launch_bounds__(256) void k_syr2k_bf16(
         *reinterpret_cast<bf16x8*>(&tile(which)[lr][lk]) = hv;
         *reinterpret_cast<bf16x8*>(&tile(which + 1)[lr][lk]) = lv;
     };
-    auto put_phi = [&](int which, const ulonglong2 (&g)[4], bool valid) {
+    auto put_phi = [&](int which, const v2u64 (&g)[4], bool valid) {
         const unsigned long long w[8] = {g[0].x, g[0].y, g[1].x, g[1].y,
                                          g[2].x, g[2].y, g[3].x, g[3].y};
         bf16x8 hv, lv;

@@ -619,8 +619,12 @@ int launch_ssf(xc_context* c) {
     }
     if (c->natoms <= kSsfWaveMaxAtoms) {
         const int nper = (c->natoms + 63) / 64;
+        // atom slots per lane: the fewest instantiated that cover the atoms
+        // (a slot past the last atom still costs its share of the work)
         auto k = nper <= 1 ? k_ssf_wave<1> : nper <= 2 ? k_ssf_wave<2>
-               : nper <= 4 ? k_ssf_wave<4> : nper <= 8 ? k_ssf_wave<8> : k_ssf_wave<16>;
+               : nper <= 4 ? k_ssf_wave<4> : nper <= 6 ? k_ssf_wave<6>
+               : nper <= 8 ? k_ssf_wave<8> : nper <= 10 ? k_ssf_wave<10>
+               : nper <= 12 ? k_ssf_wave<12> : k_ssf_wave<16>;
         hipLaunchKernelGGL(k, dim3(grid_1d(c->n_nominal, 256)), dim3(256),
                            sizeof(double4) * (size_t)c->natoms, c->stream, c->n_nominal, npa,
                            (const int*)c->d_gatoms.p, (const double4*)c->d_atoms.p,

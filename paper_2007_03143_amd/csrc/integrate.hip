@@ -627,19 +627,19 @@ __device__ __forceinline__ void gemm_rho_tile(
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const int wm = wave >> 1, wn = wave & 1;
     const int nk = B.nbp / 16;
-    // The 16 column indices of a K step are loaded once, by threads 0-15,
-    // and passed on through a ring of four LDS slots (slot = step mod 4).
-    int fnext = -1;
-    auto fetch = [&](int ks) {
-        if (tid < 16) {
-            const int k = ks * 16 + tid;
-            fnext = k < B.nb ? fl[k] : -1;
-        }
-    };
+    // The 16 column indices of a K step are passed on through a ring of
+    // four LDS slots (slot = step mod 4), written by threads 0-15; a padding
+    // column (k >= n_b) holds the last function's index and is zeroed at
+    // the LDS store by its position. Every thread loads, so that each step
+    // issues the same number of loads on every path, and the loaded index is
+    // not touched before its ring store a step later: the waits for older
+    // loads can then leave the newer ones in flight.
+    int fnext = 0;
+    auto fetch = [&](int ks) { fnext = fl[min(ks * 16 + (tid & 15), B.nb - 1)]; };
     auto fput = [&](int ks) {
         if (tid < 16) sfl[ks & 3][tid] = fnext;
     };
-    for (int s0 = 0; s0 < 3 && s0 < nk; ++s0) {
+    for (int s0 = 0; s0 < 3; ++s0) {
         fetch(s0);
         fput(s0);
     }
@@ -657,9 +657,9 @@ __device__ __forceinline__ void gemm_rho_tile(
 
     // Two register sets: the operands of step ks + 2 are loaded while step
     // ks is computed and those of step ks + 1 wait in the other set. The P^j
-    // columns of a step are gathered through the function list. FP32: the P
-    // values stay FP64 until the LDS store, where they are rounded and the
-    // padding is selected away, all loads going to valid (clamped) addresses.
+    // columns of a step are gathered through the function list. The P
+    // values stay FP64 until the LDS store, where they are rounded (FP32) and
+    // the padding is selected away.
     struct Regs {
         T ra[4], rb[4 * NW];
         double pv[4];
@@ -673,29 +673,27 @@ __device__ __forceinline__ void gemm_rho_tile(
         r.fc[2] = v.z;
         r.fc[3] = v.w;
     };
+    // All loads go to valid (clamped) addresses and none is skipped: a
+    // padding entry of P^j is selected away at the LDS store, a K step past
+    // the last reloads the last one's Phi rows, and a 64-point half past the
+    // slab's end reloads the first half (its blocks are not computed).
     auto gload = [&](Regs& r, int ks) {
-        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) r.pv[q] = Prow[r.fc[q] >= 0 ? r.fc[q] : 0];
-        } else {
+        for (int q = 0; q < 4; ++q) r.pv[q] = Prow[r.fc[q]];
+        const gptr<const T> src =
+            Phi + (size_t)(min(ks, nk - 1) * 16 + br) * B.ngp + n0 + bc;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                r.ra[q] = (fr >= 0 && r.fc[q] >= 0) ? T(Prow[r.fc[q]]) : T(0);
+        for (int w = 0; w < NW; ++w) {
+            const int off = (w == 0 || w * kTile < ncol) ? kTile * w : 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r.rb[4 * w + q] = src[off + q];
         }
-        const gptr<const T> src = Phi + (size_t)(ks * 16 + br) * B.ngp + n0 + bc;
-#pragma unroll
-        for (int w = 0; w < NW; ++w)
-            if (w == 0 || w * kTile < ncol) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) r.rb[4 * w + q] = src[kTile * w + q];
-            }
     };
-    auto sstore = [&](Regs& r, int buf) {
-        if constexpr (sizeof(T) == 4) {
+    auto sstore = [&](Regs& r, int ks) {
+        const int buf = ks & 1;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                r.ra[q] = (fr >= 0 && r.fc[q] >= 0) ? T(r.pv[q]) : T(0);
-        }
+        for (int q = 0; q < 4; ++q)
+            r.ra[q] = (fr >= 0 && ks * 16 + ac + q < B.nb) ? T(r.pv[q]) : T(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             As[buf][ar][ac + q] = r.ra[q];
@@ -729,21 +727,19 @@ __device__ __forceinline__ void gemm_rho_tile(
     fread(RA, 0);
     gload(RA, 0);
     sstore(RA, 0);
-    if (nk > 1) {
-        fread(RB, 1);
-        gload(RB, 1);
-    }
-    if (nk > 3) fetch(3);
+    fread(RB, 1);
+    gload(RB, 1);
+    fetch(3);
     __syncthreads();
     // step ks: load step ks + 2 into rl, compute from LDS buffer ks & 1,
     // store step ks + 1 from rs into the other buffer; then refill the ring
-    // slot of step ks + 3 (last read three steps ago) and fetch step ks + 4
+    // slot of step ks + 3 (last read three steps ago) and fetch step ks + 4.
+    // Steps past the last load and store clamped, valid indices, so every
+    // slot a step reads holds one.
     auto step = [&](int ks, Regs& rl, Regs& rs) {
         const int cur = ks & 1;
-        if (ks + 2 < nk) {
-            fread(rl, ks + 2);
-            gload(rl, ks + 2);
-        }
+        fread(rl, ks + 2);
+        gload(rl, ks + 2);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             T a[2], b[NB];
@@ -759,11 +755,9 @@ __device__ __forceinline__ void gemm_rho_tile(
                 for (int nb = 0; nb < NB; ++nb)
                     if (live[mb][nb]) acc[mb][nb] = M::mma(a[mb], b[nb], acc[mb][nb]);
         }
-        if (ks + 1 < nk) sstore(rs, cur ^ 1);
-        if (ks + 3 < nk) {
-            fput(ks + 3);
-            if (ks + 4 < nk) fetch(ks + 4);
-        }
+        if (ks + 1 < nk) sstore(rs, ks + 1);
+        fput(ks + 3);
+        fetch(ks + 4);
         __syncthreads();
     };
     for (int ks = 0; ks < nk; ks += 2) {

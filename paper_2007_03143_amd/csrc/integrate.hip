@@ -18,6 +18,7 @@
 //     added into the lower triangle of the full V with FP64 atomics.
 // Then V is mirrored and E_xc, N_e are summed in a fixed order.
 #include <cmath>
+#include <type_traits>
 
 #include "device_util.hpp"
 #include "functional.hpp"
@@ -1161,10 +1162,13 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const gptr<const T> Zm = (gptr<const T>)to_global(scratch + 8 * B.z_off);
     const gptr<const int> fl = func_list + B.func_off;
 
-    // K steps of 8. FP64: one LDS buffer (the next step's operands wait in
-    // registers), 19 KB, so the register count (five workgroups per CU) sets
-    // the occupancy, not LDS (four with two buffers: measured slower). FP32
-    // arithmetic: two buffers (measured faster there).
+    // K steps of 8. FP64: one LDS buffer, 19 KB, and two register sets (the
+    // operands of the next two steps), so the register count (four
+    // workgroups per CU) sets the occupancy, not LDS; one register set fits
+    // five workgroups per CU but waits for each step's loads within the
+    // step (1.4 % slower on the chain), and so does forcing five with two
+    // sets (registers spilled). FP32 arithmetic: two LDS buffers (measured
+    // faster there).
     constexpr int KS = 8;
     // row pitch: 9 doubles, or 12 floats (the 4-byte operand reads of a wave
     // then fall in distinct banks)
@@ -1197,10 +1201,10 @@ __global__ __launch_bounds__(256) void k_syr2k(
     const gptr<const T> zJ = Zm + (size_t)(vJ ? rJ : 0) * B.ngp;
     const gptr<const TP> pJ = Phi + (size_t)(vJ ? rJ : 0) * B.ngp;
 
-    // FP32: loads from the clamped (always valid) rows, padding rows zeroed
-    // after the load, so no branch separates the loads (with a branch around
-    // each, the 4-byte loads were issued and waited for one at a time). FP64:
-    // rows past the padded count are not loaded at all.
+    // FP32 (one register set, two LDS buffers): loads from the clamped
+    // (always valid) rows, padding rows zeroed after the load, so no branch
+    // separates the loads (with a branch around each, the 4-byte loads were
+    // issued and waited for one at a time).
     T g[4][2];
     auto gload = [&](int ks) {
         const int k0 = ks * KS + lc;
@@ -1228,19 +1232,6 @@ __global__ __launch_bounds__(256) void k_syr2k(
                 for (int q = 0; q < 2; ++q) {
                     g[2][q] = vJ ? T(ph[1][q]) : T(0);
                     g[3][q] = vJ ? g[3][q] : T(0);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                g[0][q] = vI ? zI[k0 + q] : T(0);
-                g[1][q] = vI ? pI[k0 + q] : T(0);
-            }
-            if (!diag) {
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    g[2][q] = vJ ? pJ[k0 + q] : T(0);
-                    g[3][q] = vJ ? zJ[k0 + q] : T(0);
                 }
             }
         }
@@ -1277,12 +1268,8 @@ __global__ __launch_bounds__(256) void k_syr2k(
             const int c0 = J * kTile + wn * 32 + nb * 16;
             live[mb][nb] = (r0 < B.nb) && (c0 < B.nb) && (c0 <= r0 + 15);
         }
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int ks = 0; ks < nk; ++ks) {
-        const int cur = NBUF == 1 ? 0 : (ks & 1);
-        if (ks + 1 < nk) gload(ks + 1);
+    // one K step of 8 from LDS buffer cur
+    auto compute = [&](int cur) {
 #pragma unroll
         for (int kk = 0; kk < KS / 4; ++kk) {
             const int kc = kk * 4 + (lane >> 4);
@@ -1308,13 +1295,74 @@ __global__ __launch_bounds__(256) void k_syr2k(
                     acc[mb][nb] = M::mma(ap[mb], bz[nb], acc[mb][nb]);
                 }
         }
-        if constexpr (NBUF == 1) {
+    };
+    if constexpr (NBUF == 1) {
+        // FP64: two register sets, the operands of step ks + 2 loading while
+        // step ks is computed and those of step ks + 1 waiting to be stored.
+        // Every step issues the same loads (clamped rows and steps; padding
+        // rows zeroed at the store; a diagonal tile's loop is compiled
+        // apart, without its column operands), so the wait before a store
+        // leaves the newer step's loads in flight.
+        T ga[4][2], gb[4][2];
+        auto run = [&](auto dtag) {
+            constexpr bool D = decltype(dtag)::value;
+            auto load2 = [&](int ks, T (&gg)[4][2]) {
+                const int k0 = min(ks, nk - 1) * KS + lc;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    gg[0][q] = zI[k0 + q];
+                    gg[1][q] = pI[k0 + q];
+                }
+                if constexpr (!D) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        gg[2][q] = pJ[k0 + q];
+                        gg[3][q] = zJ[k0 + q];
+                    }
+                }
+            };
+            auto store2 = [&](const T (&gg)[4][2]) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    sZI[0][lr][lc + q] = vI ? gg[0][q] : T(0);
+                    sPI[0][lr][lc + q] = vI ? gg[1][q] : T(0);
+                }
+                if constexpr (!D) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        sPJ[0][lr][lc + q] = vJ ? gg[2][q] : T(0);
+                        sZJ[0][lr][lc + q] = vJ ? gg[3][q] : T(0);
+                    }
+                }
+            };
+            load2(0, ga);
+            store2(ga);
+            load2(1, gb);
             __syncthreads();
-            if (ks + 1 < nk) {
-                sstore(0);
+            auto step = [&](int ks, T (&gl)[4][2], T (&gs)[4][2]) {
+                load2(ks + 2, gl);
+                compute(0);
                 __syncthreads();
+                if (ks + 1 < nk) {
+                    store2(gs);
+                    __syncthreads();
+                }
+            };
+            for (int ks = 0; ks < nk; ks += 2) {
+                step(ks, ga, gb);
+                if (ks + 1 < nk) step(ks + 1, gb, ga);
             }
-        } else {
+        };
+        if (diag) run(std::true_type{});
+        else run(std::false_type{});
+    } else {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int ks = 0; ks < nk; ++ks) {
+            const int cur = ks & 1;
+            if (ks + 1 < nk) gload(ks + 1);
+            compute(cur);
             if (ks + 1 < nk) sstore(cur ^ 1);
             __syncthreads();
         }

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define XC_ABI_VERSION 2
+#define XC_ABI_VERSION 3
 
 /* return codes */
 #define XC_OK               0
@@ -178,10 +178,32 @@ typedef struct xc_grid_spec {
  *  wave_bytes  budget of device scratch for one wave of batches (the
  *              subsets of batches that fill the device memory, Alg. 2); 0:
  *              min(half the free device memory, 48 GiB).
+ *  alloc, free caller-supplied device allocator (a framework's caching
+ *              allocator, an arena of its own), both set or both NULL
+ *              (NULL: hipMalloc and hipFree). Every device buffer the
+ *              context holds is obtained with alloc(bytes, alloc_user),
+ *              which returns a device pointer to at least `bytes` bytes or
+ *              NULL on failure, and is given back with free(ptr,
+ *              alloc_user) when it grows, on xc_context_release and on
+ *              xc_context_destroy (after the context's stream has been
+ *              synchronised there). The library uses the memory on the
+ *              context's stream only; an allocator that hands out
+ *              stream-ordered memory must tie it to that stream. A NULL
+ *              from alloc makes the call that needed the memory return
+ *              XC_ERR_NOMEM; the context stays valid and can be released or
+ *              destroyed. The callbacks run on the calling thread, inside
+ *              the library's entry points; they must not call back into
+ *              the same context.
  */
+typedef void* (*xc_alloc_fn)(size_t bytes, void* user);
+typedef void (*xc_free_fn)(void* ptr, void* user);
+
 typedef struct xc_device_opts {
     void* stream;
     size_t wave_bytes;
+    xc_alloc_fn alloc;
+    xc_free_fn free;
+    void* alloc_user;
 } xc_device_opts;
 
 /* Sizes of a built grid; all counts refer to the points actually integrated. */

@@ -61,8 +61,15 @@ class XcGridSpec(Structure):
                 ("becke_radius", POINTER(c_double))]
 
 
+# device allocator callbacks: void* alloc(size_t bytes, void* user) and
+# void free(void* ptr, void* user)
+XC_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+XC_FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
 class XcDeviceOpts(Structure):
-    _fields_ = [("stream", c_void_p), ("wave_bytes", c_size_t)]
+    _fields_ = [("stream", c_void_p), ("wave_bytes", c_size_t), ("alloc", XC_ALLOC_FN),
+                ("free", XC_FREE_FN), ("alloc_user", c_void_p)]
 
 
 class XcStats(Structure):
@@ -269,9 +276,16 @@ def xc_integrate(coords, mk_alpha, basis, grid, functional, P, precision="fp64")
     return E.value, N.value, V
 
 
-def xc_context_create(coords, mk_alpha, basis, grid, stream=0, wave_bytes=0):
+def xc_context_create(coords, mk_alpha, basis, grid, stream=0, wave_bytes=0, alloc=None,
+                      free=None):
+    """alloc, free: XC_ALLOC_FN and XC_FREE_FN callback objects (the caller
+    keeps them alive as long as the context), or None for hipMalloc."""
     inp = _Inputs(coords, mk_alpha, basis, grid)
     opts = XcDeviceOpts(c_void_p(int(stream)), int(wave_bytes))
+    if alloc is not None:
+        opts.alloc = alloc
+    if free is not None:
+        opts.free = free
     h = c_void_p()
     _check(LIB.xc_context_create(byref(inp.mol), byref(inp.basis), byref(inp.grid),
                                  byref(opts), byref(h)))
@@ -417,12 +431,41 @@ class XcContext:
     """A device context whose P, V and E/N buffers are torch tensors on the
     current device, with launches ordered on torch's current stream."""
 
-    def __init__(self, coords, mk_alpha, basis, grid, wave_bytes=0, stream=None):
+    def __init__(self, coords, mk_alpha, basis, grid, wave_bytes=0, stream=None,
+                 allocator=None):
+        """allocator: None (the library's hipMalloc), "torch" (torch's caching
+        allocator on the context's stream) or a pair (alloc, free) of Python
+        callables, alloc(nbytes) -> device address (0 on failure) and
+        free(address)."""
         import torch
         self.torch = torch
+        self.handle = None
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._alloc_cb = self._free_cb = None
+        if allocator is not None:
+            if allocator == "torch":
+                dev, st = torch.cuda.current_device(), self.stream
+
+                def py_alloc(n):
+                    return torch.cuda.caching_allocator_alloc(n, dev, st)
+
+                py_free = torch.cuda.caching_allocator_delete
+            else:
+                py_alloc, py_free = allocator
+
+            def c_alloc(n, _user):
+                try:
+                    return int(py_alloc(int(n))) or None
+                except Exception:
+                    return None
+
+            def c_free(p, _user):
+                py_free(int(p))
+
+            self._alloc_cb, self._free_cb = XC_ALLOC_FN(c_alloc), XC_FREE_FN(c_free)
         self.handle, self.nbf = xc_context_create(coords, mk_alpha, basis, grid,
-                                                  self.stream.cuda_stream, wave_bytes)
+                                                  self.stream.cuda_stream, wave_bytes,
+                                                  self._alloc_cb, self._free_cb)
         self.V = torch.empty((self.nbf, self.nbf), dtype=torch.float64, device="cuda")
         self.EN = torch.empty(2, dtype=torch.float64, device="cuda")
 

@@ -29,6 +29,17 @@ int hip_fail(hipError_t e, const char* what) {
 int dev_reserve(DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 8;
     if (b.p && b.cap >= bytes) return XC_OK;
+    if (b.al) {
+        if (b.p) b.al->free(b.p, b.al->user);
+        b.p = b.al->alloc(bytes, b.al->user);
+        if (!b.p) {
+            b.cap = 0;
+            return fail(XC_ERR_NOMEM, "device allocator returned NULL for " +
+                                          std::to_string(bytes) + " bytes");
+        }
+        b.cap = bytes;
+        return XC_OK;
+    }
     if (b.p) {
         hipError_t e = hipFree(b.p);
         b.p = nullptr;
@@ -46,7 +57,10 @@ int dev_reserve(DevBuf& b, size_t bytes) {
 }
 
 void dev_release(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) {
+        if (b.al) b.al->free(b.p, b.al->user);
+        else (void)hipFree(b.p);
+    }
     b.p = nullptr;
     b.cap = 0;
 }
@@ -228,8 +242,9 @@ static int check_func_prec(int functional, int precision) {
     return XC_OK;
 }
 
-static void release_all(xc_context* c) {
-    DevBuf* bufs[] = {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
+// Every device buffer of a context.
+static std::vector<DevBuf*> all_buffers(xc_context* c) {
+    return {&c->d_atoms, &c->d_invR, &c->d_nnhalf, &c->d_shells, &c->d_palpha,
                       &c->d_pcoef, &c->d_ang, &c->d_gatoms, &c->d_fshell, &c->d_nbr_idx, &c->d_nbr_R, &c->d_becke_a,
                       &c->raw_x, &c->raw_y,
                       &c->raw_z, &c->raw_w, &c->px, &c->py, &c->pz, &c->pw, &c->pidx,
@@ -240,7 +255,10 @@ static void release_all(xc_context* c) {
                       &c->shell_list, &c->shell_loff, &c->func_list, &c->d_wb,
                       &c->d_gemm_pre, &c->d_syr_pre, &c->d_wide_pre, &c->d_tmap, &c->scratch, &c->epart,
                       &c->npart, &c->d_req, &c->pdig, &c->pscale, &c->d_wb_beta, &c->d_wb_meta};
-    for (DevBuf* b : bufs) dev_release(*b);
+}
+
+static void release_all(xc_context* c) {
+    for (DevBuf* b : all_buffers(c)) dev_release(*b);
 }
 
 // Split the batches into consecutive waves whose scratch (Phi and its
@@ -450,6 +468,14 @@ int xc_context_create(const xc_molecule* mol, const xc_basis* basis,
     if (!c) return fail(XC_ERR_NOMEM, "host allocation failed");
     c->stream = opts ? (hipStream_t)opts->stream : nullptr;
     c->wave_budget = opts ? opts->wave_bytes : 0;
+    if (opts && (opts->alloc || opts->free)) {
+        if (!opts->alloc || !opts->free) {
+            delete c;
+            return fail(XC_ERR_INVALID_ARG, "set both alloc and free, or neither");
+        }
+        c->alloc = {opts->alloc, opts->free, opts->alloc_user};
+        for (DevBuf* b : all_buffers(c)) b->al = &c->alloc;
+    }
     c->natoms = mol->natoms;
     c->atoms4.resize(4 * (size_t)c->natoms);
     for (int a = 0; a < c->natoms; ++a) {

@@ -193,9 +193,18 @@ struct Wave {
 };
 
 // ------------------------------------------------------------- context ----
+// A caller-supplied device allocator (both callbacks set).
+struct DevAlloc {
+    xc_alloc_fn alloc = nullptr;
+    xc_free_fn free = nullptr;
+    void* user = nullptr;
+};
+
+// A device buffer; memory from `al` when set, else from hipMalloc.
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    const DevAlloc* al = nullptr;
 };
 
 // HIP-event phase timer: pairs of events recorded around launches, folded
@@ -213,6 +222,7 @@ struct PhaseTimer {
 struct xc_context {
     hipStream_t stream = nullptr;
     int device = 0;
+    xc::DevAlloc alloc;          // the caller's allocator (alloc == nullptr: hipMalloc)
 
     // inputs (host copies)
     int natoms = 0;

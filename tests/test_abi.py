@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_messages():
     import paper_2007_03143_amd as pkg
-    assert pkg.xc_abi_version() == 2
+    assert pkg.xc_abi_version() == 3
     assert pkg.xc_strerror(0) == "ok"
     assert pkg.xc_strerror(pkg.XC_ERR_NOMEM) == "out of device memory"
     assert pkg.xc_strerror(-99) == "unknown error"
@@ -101,3 +101,17 @@ def test_spherical_flags_and_becke_size_limits_rejected():
     with pytest.raises(pkg.XcError) as e:
         pkg.xc_integrate(X, np.full(1200, 5.0), hb, grid, "lda", np.zeros((hb.nbf, hb.nbf)))
     assert e.value.code == pkg.XC_ERR_UNSUPPORTED
+
+
+def test_allocator_needs_both_callbacks():
+    """A device allocator with alloc but no free (or the reverse) is refused
+    before any device call."""
+    import paper_2007_03143_amd.binding as b
+    w, g = _water()
+    alloc = b.XC_ALLOC_FN(lambda n, user: None)
+    free = b.XC_FREE_FN(lambda p, user: None)
+    for a, f in ((alloc, None), (None, free)):
+        with pytest.raises(b.XcError) as e:
+            b.xc_context_create(w.coords, w.mk_alpha, w.basis, g, 0, 0, a, f)
+        assert e.value.code == b.XC_ERR_INVALID_ARG
+        assert "alloc" in str(e.value)

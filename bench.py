@@ -436,6 +436,29 @@ def cpu_baseline(w, functional, atom, stride, extrapolate):
         out["extrapolated_whole_workload_s"] = w.n_points_nominal / rate
         out["note"] = ("rate measured on the sample; the whole workload's oracle time is "
                        "extrapolated from it (nominal points / rate)")
+    # the same oracle on one BLAS thread, on a four times sparser sample
+    try:
+        from threadpoolctl import threadpool_limits
+        sl1 = slice(0, None, 4 * stride)
+        n1 = len(range(*sl1.indices(n_atom)))
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.integrate(w.coords, w.mk_alpha, w.basis, w.P, functional, w.n_rad, w.ang,
+                             atom_mask=mask, point_slice=sl1)
+            dt1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": n1 / dt1, "unit": "grid points/s", "cores": 1,
+                                "sample": f"{n1} points (every {4 * stride}th point of the "
+                                          f"same parent atom); {dt1:.1f} s"}
+    except ImportError:
+        pass
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                         "")
+    except OSError:
+        pass
+    out["host"] = {"nproc": os.cpu_count(), "cpu_model": model}
     return out
 
 

@@ -58,3 +58,21 @@ def oracle_integrate(w, functional, atom_mask=None, P=None, **grid_over):
 def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+_CHAIN = {}
+
+
+def chain600(n_rad=99, n_ang=590):
+    """The 600-atom chain workload on an n_rad x n_ang grid. Its basis, S and
+    P do not depend on the grid, so they are built once per process and
+    shared (building them takes tens of seconds)."""
+    import dataclasses
+    from workloads import cfg_chain
+    if "base" not in _CHAIN:
+        say("  building the 600-atom chain workload (basis, S, P)")
+        _CHAIN["base"] = cfg_chain()
+    base = _CHAIN["base"]
+    if (n_rad, n_ang) == (base.n_rad, base.n_ang):
+        return base
+    return dataclasses.replace(base, n_rad=n_rad, n_ang=n_ang, ang=None)

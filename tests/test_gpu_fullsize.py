@@ -10,7 +10,6 @@ additivity over disjoint sets of parent atoms, independence of the batch
 size, the electron count tr(PS) recovered by the grid, and the FP32
 potential mode reproducing the FP64 density results bit for bit.
 """
-import functools
 
 import numpy as np
 import pytest
@@ -20,11 +19,10 @@ from gpu_util import say
 pytestmark = pytest.mark.gpu
 
 
-@functools.lru_cache(maxsize=1)
 def _chain():
-    from workloads import cfg_chain
-    say("case chain600 full size: building the workload")
-    return cfg_chain()
+    from gpu_util import chain600
+    say("case chain600 full size")
+    return chain600()
 
 
 def _run(w, precision="fp64", atom_mask=None, **over):

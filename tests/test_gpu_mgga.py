@@ -68,6 +68,22 @@ def test_indefinite_density_parity():
     _compare("tpss", gpu_integrate(w, "tpss", P=P), o)
 
 
+def test_chain_atom_wide_tiles_parity():
+    """One H parent atom of the 600-atom chain on a small grid (12 x 26
+    points; partition over all 600 atoms, 6280 functions): its batches
+    screen in more than 512 functions, so the density passes (rho and the
+    three gradient slabs of tau) run on 64 x 128 tiles."""
+    from gpu_util import chain600
+    w = chain600(n_rad=12, n_ang=26)
+    mask = np.zeros(w.natoms, np.uint8)
+    mask[int(np.nonzero(w.mol.Z == 1)[0][7])] = 1
+    say("case tpss chain600 one H atom 12 x 26")
+    g = gpu_integrate(w, "tpss", atom_mask=mask)
+    say(f"  waves {g[3]['n_waves']} wide {g[3]['n_wide_waves']} max n_b {g[3]['max_nb']}")
+    assert g[3]["n_wide_waves"] == g[3]["n_waves"] > 0
+    _compare("tpss", g, _oracle(w, atom_mask=mask))
+
+
 def test_context_switches_between_plans():
     """On one context: PBE, TPSS (re-plans with the meta-GGA room), PBE
     again: the restricted results are unchanged bit for bit in E_xc and N_e."""

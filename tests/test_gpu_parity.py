@@ -258,9 +258,9 @@ def test_chain600_sampled_atoms_parity():
     radial x angular grid is reduced (30 x 50) so that the oracle's all-pairs
     partition over the two sampled parent atoms (a C and an H) stays short;
     the GPU still builds, partitions and batches every atom's grid."""
-    from workloads import cfg_chain
+    from gpu_util import chain600
     say("case chain600 build workload")
-    w = cfg_chain(n_rad=30, n_ang=50)
+    w = chain600(n_rad=30, n_ang=50)
     mask = np.zeros(w.natoms, np.uint8)
     heavy = int(np.nonzero(w.mol.Z == 6)[0][3])
     light = int(np.nonzero(w.mol.Z == 1)[0][7])
@@ -541,10 +541,10 @@ def test_chain600_full_grid_atoms_match_golden():
     reach screened function counts above 2048 (more than 32 row tiles)."""
     import json
     import os
-    from workloads import cfg_chain
+    from gpu_util import chain600
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                        "chain600_atoms.json")))
-    w = cfg_chain()
+    w = chain600()
     assert (w.n_rad, w.n_ang, w.nbf) == (gold["n_rad"], gold["n_ang"], gold["nbf"])
     for g in gold["atoms"]:
         mask = np.zeros(w.natoms, np.uint8)

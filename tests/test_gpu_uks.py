@@ -97,6 +97,26 @@ def test_closed_shell_uks_equals_rks(functional):
     assert np.abs(Va - Vr).max() <= 1e-13 * np.abs(Vr).max()
 
 
+def test_closed_shell_uks_equals_rks_on_wide_tiles():
+    """The 600-atom chain on two parent atoms of a reduced grid: its batches
+    screen in several hundred functions, so every wave's FP64 density
+    contraction runs on 64 x 128 tiles, for both spins. P^a = P^b = P/2
+    gives the restricted E, N and V."""
+    from gpu_util import chain600
+    w = chain600(n_rad=30, n_ang=50)
+    mask = np.zeros(w.natoms, np.uint8)
+    mask[[int(np.nonzero(w.mol.Z == 6)[0][3]), int(np.nonzero(w.mol.Z == 1)[0][7])]] = 1
+    say("case uks closed shell chain600 two atoms, 64 x 128 tiles")
+    E, N, Va, Vb, st, (Er, Nr, Vr) = _gpu_uks(w, w.P / 2, w.P / 2, "pbe", also_rks=w.P,
+                                               atom_mask=mask)
+    say(f"  waves {st['n_waves']} wide {st['n_wide_waves']} dE {E - Er:.3e} dN {N - Nr:.3e} "
+        f"max dVa {np.abs(Va - Vr).max():.3e}")
+    assert st["n_wide_waves"] == st["n_waves"] > 0
+    assert abs(E - Er) <= 1e-12 * abs(Er) and abs(N - Nr) <= 1e-12 * abs(Nr)
+    assert np.abs(Va - Vr).max() <= 1e-13 * np.abs(Vr).max()
+    assert np.abs(Vb - Vr).max() <= 1e-13 * np.abs(Vr).max()
+
+
 def test_cluster_many_waves_parity():
     """Eight waters on a 30 x 86 grid, split over several waves, PBE."""
     w = cfg_water_cluster(8, n_rad=30, n_ang=86)

@@ -48,6 +48,7 @@ extern "C" {
 #define XC_ERR_NOMEM       (-3)  /* device memory exhausted or budget too small */
 #define XC_ERR_DEVICE      (-4)  /* a HIP runtime call or kernel launch failed */
 #define XC_ERR_STATE       (-5)  /* call not valid in the context's current state */
+#define XC_ERR_BUSY        (-6)  /* the object still has work in flight (retry later) */
 
 /* exchange-correlation functionals (spin-unpolarised) */
 #define XC_LDA_SVWN5 1   /* Slater exchange + VWN5 correlation */
@@ -500,7 +501,8 @@ int xc_engine_step(xc_engine* eng, int* n_batches);
  * ticket reported done is retired and cannot be polled again. */
 int xc_engine_poll(xc_engine* eng, long long ticket, int* done);
 
-/* Drop a request with no integration in flight; frees its device memory. */
+/* Drop a request with no integration in flight; frees its device memory.
+ * XC_ERR_BUSY while one of its integrations is queued or running. */
 int xc_engine_release(xc_engine* eng, long long req_id);
 
 int xc_engine_stats(xc_engine* eng, xc_engine_info* out);

@@ -16,7 +16,7 @@ from .binding import (XcContext, XcError, xc_abi_version, xc_context_build_grid,
                       xc_engine_step, xc_engine_poll, xc_engine_release,
                       xc_engine_stats, xc_engine_destroy,
                       xc_strerror, XC_OK, XC_ERR_INVALID_ARG, XC_ERR_UNSUPPORTED,
-                      XC_ERR_NOMEM, XC_ERR_DEVICE, XC_ERR_STATE, XC_LDA_SVWN5,
+                      XC_ERR_NOMEM, XC_ERR_DEVICE, XC_ERR_STATE, XC_ERR_BUSY, XC_LDA_SVWN5,
                       XC_GGA_PBE, XC_FP64, LIB_PATH)
 
 __all__ = ["XcContext", "XcError", "xc_abi_version", "xc_context_build_grid",

@@ -22,6 +22,7 @@ XC_ERR_UNSUPPORTED = -2
 XC_ERR_NOMEM = -3
 XC_ERR_DEVICE = -4
 XC_ERR_STATE = -5
+XC_ERR_BUSY = -6
 
 XC_LDA_SVWN5 = 1
 XC_GGA_PBE = 2

@@ -449,6 +449,7 @@ const char* xc_strerror(int code) {
         case XC_ERR_NOMEM: return "out of device memory";
         case XC_ERR_DEVICE: return "device error";
         case XC_ERR_STATE: return "invalid state";
+        case XC_ERR_BUSY: return "busy";
         default: return "unknown error";
     }
 }

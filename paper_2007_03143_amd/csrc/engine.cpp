@@ -532,7 +532,7 @@ int xc_engine_release(xc_engine* e, long long req_id) {
     if (it == e->reqs.end()) return fail(XC_ERR_INVALID_ARG, "unknown request");
     Request* r = it->second;
     if (r->active || !r->queued.empty())
-        return fail(XC_ERR_STATE, "request still has integrations in flight");
+        return fail(XC_ERR_BUSY, "request still has integrations in flight");
     // a grid being built is the builder thread's until it is done
     if (r->building)
         while (!r->built.load(std::memory_order_acquire)) std::this_thread::yield();

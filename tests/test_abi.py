@@ -29,6 +29,7 @@ def test_version_and_messages():
     assert pkg.xc_abi_version() == 3
     assert pkg.xc_strerror(0) == "ok"
     assert pkg.xc_strerror(pkg.XC_ERR_NOMEM) == "out of device memory"
+    assert pkg.xc_strerror(pkg.XC_ERR_BUSY) == "busy"
     assert pkg.xc_strerror(-99) == "unknown error"
 
 

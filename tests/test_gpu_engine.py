@@ -108,3 +108,37 @@ def test_engine_phi_cache_same_results_fewer_collocations(precision):
         for (E0, N0, V0), (E1, N1, V1) in zip(a.results, b.results):
             assert E0 == E1 and N0 == N1
             assert np.abs(V0 - V1).max() <= 1e-13 * np.abs(V0).max()
+
+
+def test_release_with_work_in_flight_is_busy():
+    """xc_engine_release of a request with a queued integration returns
+    XC_ERR_BUSY and leaves it intact; once its ticket polls done the same
+    release succeeds."""
+    import torch
+    import paper_2007_03143_amd as pkg
+    from paper_2007_03143_amd.serving import XcEngine
+    r = _requests(n=1, n_iter=1)[0]
+    eng = XcEngine()
+    try:
+        rid, nbf = eng.add(r)
+        P = torch.from_numpy(r.densities[0]).cuda()
+        V = torch.empty((nbf, nbf), dtype=torch.float64, device="cuda")
+        EN = torch.empty(2, dtype=torch.float64, device="cuda")
+        t = eng.submit(rid, P, V, EN)
+        with pytest.raises(pkg.XcError) as e:
+            eng.release(rid)
+        assert e.value.code == pkg.XC_ERR_BUSY
+        import time
+        done, t0 = False, time.monotonic()
+        while not done and time.monotonic() - t0 < 60.0:
+            eng.step()
+            done = eng.poll(t)
+            if not done:
+                time.sleep(0.001)   # the grid is built on the engine's builder thread
+        assert done
+        torch.cuda.synchronize()
+        eng.release(rid)
+        E0 = _alone(r)[0][0]
+        assert abs(float(EN[0]) - E0) <= 1e-12 * abs(E0)
+    finally:
+        eng.close()

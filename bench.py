@@ -34,6 +34,7 @@ METRIC = ("grid points/s for E_xc+V_xc (FP64 vs mixed at stated err); "
           "p50/p99 req latency")
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,6 +73,17 @@ def nb_histogram(ctx, w, width=128):
     tot = max(float(ng.sum()), 1.0)
     return {f"{k * width}-{(k + 1) * width - 1}": round(float(v) / tot, 4)
             for k, v in enumerate(h) if v > 0}
+
+
+def batch_sums(ctx, w):
+    """Sum n_b^2, Sum n_b n_g and Sum n_b^2 n_g over the context's screened
+    batches."""
+    pp, _, sp, sh = ctx.export_batches()
+    nf = w.basis.shell_nfunc[sh]
+    csum = np.concatenate(([0], np.cumsum(nf)))
+    nb = (csum[sp[1:]] - csum[sp[:-1]]).astype(np.float64)
+    ng = np.diff(pp).astype(np.float64)
+    return float((nb * nb).sum()), float((nb * ng).sum()), float((nb * nb * ng).sum())
 
 
 def profiled_traffic(kernel, workload, sha):
@@ -290,6 +302,18 @@ def mixed_section(ctx, P, w, functional, precs, ref, steps):
                      "dE_xc_vs_fp64": float(ENm[0] - EN[0]),
                      "dN_e_vs_fp64": float(ENm[1] - EN[1]),
                      "max_dV_vs_fp64": float(np.abs(Vm - V).max())}
+        if prec == "bf16" and tm.get("density", {}).get("launches"):
+            # the split-BF16 density contraction against both of its bounds:
+            # must-move bytes (the gathered P^j digits and the Phi digits, 8 B
+            # per element each) over HBM, and the BF16 MFMA work of its ten
+            # digit products over the dense BF16 peak
+            s_nb2, s_nbng, s_nb2ng = batch_sums(ctx, w)
+            t = tm["density"]["ms"] / 3 * 1e-3
+            out[prec]["density_roofline"] = {
+                "must_move_bytes": 8.0 * (s_nb2 + s_nbng),
+                "hbm_frac": 8.0 * (s_nb2 + s_nbng) / t / (PEAK_HBM_GBS * 1e9),
+                "bf16_mfma_flop": 10 * 2.0 * s_nb2ng,
+                "bf16_mfma_frac": 10 * 2.0 * s_nb2ng / t / (PEAK_BF16_MFMA_TFLOPS * 1e12)}
         log(f"  {prec}: {ms_m:.1f} ms/step ({ms_warm / ms_m:.2f}x), "
             f"dE vs fp64 {ENm[0] - EN[0]:.3e}")
     return out
